@@ -1,0 +1,208 @@
+/*
+ * lbsq.h -- C ABI of the MI355X (gfx950) lattice Boltzmann squirmer library.
+ *
+ * The library advances the lattice Boltzmann squirmer model of Kuron,
+ * Staerk, Burkard, de Graaf and Holm, "A Lattice Boltzmann Model for
+ * Squirmers" (arXiv:1903.04799):
+ *   - a D3Q19 fluid with the two-relaxation-time collision of Sec.
+ *     "Numerical Method", eq. (lb), in a fully periodic box;
+ *   - spherical squirmers coupled by moving-wall link bounce-back whose wall
+ *     velocity is the rigid-body velocity eq. (vb) plus the surface slip of
+ *     eq. (squirmer), B1 (1 + beta e.n)((e.n) n - e);
+ *   - momentum-exchange force and torque eqs. (bbforce), (bbtorque) and the
+ *     cell-conversion force eq. (consforce), WCA contact repulsion eq. (wca),
+ *     and symplectic-Euler rigid-body motion, all on the device.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status: LB_OK (0) or a negative LB_E* code;
+ *     lb_strerror() names it.  No C++ exception crosses this boundary.
+ *   - Lattice units throughout (grid spacing 1, time step 1).  Cell (i,j,k)
+ *     has its centre at (i+1/2, j+1/2, k+1/2).  Linear cell index
+ *     x + nx*(y + ny*z), x fastest.  Host arrays are structure-of-arrays.
+ *   - Population order (canonical, also the layout of lb_read_populations):
+ *       0 rest; 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z;
+ *       7 (+1,+1,0), 8 (-1,-1,0), 9 (+1,-1,0), 10 (-1,+1,0),
+ *       11 (+1,0,+1), 12 (-1,0,-1), 13 (+1,0,-1), 14 (-1,0,+1),
+ *       15 (0,+1,+1), 16 (0,-1,-1), 17 (0,+1,-1), 18 (0,-1,+1);
+ *     for odd i the opposite direction is i+1.
+ *   - The handle is opaque and owned by the caller until lb_destroy.  It is
+ *     not thread-safe; distinct handles may be driven concurrently.
+ *   - Device memory is owned by the library.  If lb_params.alloc/free are
+ *     given, every device allocation goes through them (for example a
+ *     framework's caching allocator); otherwise hipMalloc/hipFree are used.
+ *     All host buffers passed in are owned by the caller.
+ *   - lb_step only enqueues work on the handle's HIP stream and returns.
+ *     Calls that hand data back (lb_read_*, lb_force_torque, lb_body_state,
+ *     lb_links, lb_audit, lb_sync, lb_save_state) synchronise the stream, and
+ *     report errors detected on the device since the previous such call
+ *     (LB_EGEOM: overlapping bodies or a body moving a cell or more per step;
+ *     LB_ENAN: non-finite populations found by the periodic audit).
+ */
+#ifndef LBSQ_H
+#define LBSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,  /* bad argument */
+    LB_ENOMEM = -2,  /* device allocation failed */
+    LB_EDEVICE = -3, /* HIP runtime error */
+    LB_EGEOM = -4,   /* overlapping bodies, body too large for the box, too fast */
+    LB_ESTATE = -5,  /* call not allowed in the current state */
+    LB_ENAN = -6,    /* non-finite populations detected */
+    LB_EBUDGET = -7  /* request exceeds a memory budget */
+};
+
+enum { LB_STORAGE_F32 = 0, LB_STORAGE_F16 = 1, LB_STORAGE_BF16 = 2 };
+enum { LB_FREE = 0, LB_FIXED = 1, LB_PRESCRIBED = 2 };
+enum { LB_OWNER_FLUID = 0, LB_OWNER_WALL = 255 }; /* bodies: id + 1 */
+
+typedef void *(*lb_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*lb_free_fn)(void *ptr, void *ctx);
+
+/* Box and fluid parameters.
+ *   nx, ny, nz   box size in cells, each >= 4, nx*ny*nz < 2^32;
+ *   nu           kinematic viscosity; lambda_e = 1/(3 nu + 1/2) (the
+ *                viscosity relation of Sec. "Numerical Method");
+ *   magic        TRT product Lambda = (1/lambda_e - 1/2)(1/lambda_o - 1/2),
+ *                3/16 for halfway-exact bounce-back (the paper's printed
+ *                "lambda_o lambda_e = 3/16"); lambda_e and lambda_o must lie
+ *                in (0, 2);
+ *   rho0         reference density (fluid starts at rest with f = w_i rho0);
+ *   storage      LB_STORAGE_F32 | _F16 | _BF16: populations are stored as
+ *                deviations f_i - w_i rho0 in that type, times 2^scale_log2;
+ *                the collision is always computed in FP32;
+ *   scale_log2   power-of-two scale of stored deviations (0 for F32/BF16,
+ *                typically 14 for F16); 0..20;
+ *   wca_sigma, wca_eps   WCA range and strength, eq. (wca);
+ *   g            uniform body-force density, a test hook outside the paper's
+ *                method (default 0; nonzero only for channel-flow checks);
+ *   audit_every  fuse an FP64 mass/momentum audit and non-finite check into
+ *                the collision every this many steps (0 = never);
+ *   stream       hipStream_t to run on (NULL = the null stream);
+ *   alloc, free, alloc_ctx  optional device allocator pair.               */
+typedef struct lb_params {
+    int nx, ny, nz;
+    double nu, magic, rho0;
+    int storage;
+    int scale_log2;
+    double wca_sigma, wca_eps;
+    double g[3];
+    int audit_every;
+    void *stream;
+    lb_alloc_fn alloc;
+    lb_free_fn free;
+    void *alloc_ctx;
+} lb_params;
+
+/* One spherical squirmer, eq. (squirmer) with beta = B2/B1.
+ *   pos   centre, lattice units, any real value (wrapped into the box);
+ *   e     orientation (normalised by the library; LB_EINVAL if zero);
+ *   R     radius (> 0.5); the box must satisfy 2*(ceil(R)+4)+1 <= min(n);
+ *   B1, beta  slip amplitude and dipolarity; B1 = 0 is a no-slip sphere;
+ *   mode  LB_FREE (moves under F and T), LB_FIXED (never moves; F and T are
+ *         still measured), LB_PRESCRIBED (moves with the given v, w);
+ *   v, w  initial (FREE) or imposed (PRESCRIBED) velocity and angular
+ *         velocity; |v| must stay below one cell per step;
+ *   rho_p particle density for the mass m = rho_p 4/3 pi R^3 and moment of
+ *         inertia I = 2/5 m R^2 (<= 0 means rho0).                           */
+typedef struct lb_squirmer {
+    double pos[3], e[3];
+    double R, B1, beta;
+    int mode;
+    double v[3], w[3];
+    double rho_p;
+} lb_squirmer;
+
+typedef struct lb_sim lb_sim;
+
+/* Allocate a periodic box at rest.  LB_EINVAL for a dimension < 4, nu <= 0,
+ * relaxation rates outside (0, 2) or an unknown storage type. */
+int lb_create(const lb_params *p, lb_sim **out);
+
+/* Static no-slip walls (bounce-back with zero wall velocity, the no-slip
+ * rule of Sec. "Numerical Method"): solid[c] != 0 marks cell c as wall.  n
+ * must equal nx*ny*nz.  Only before the first step and before any body.  */
+int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n);
+
+/* Add a body (see lb_squirmer); *id receives its index (0, 1, ...).  The
+ * cells inside it become solid at once (no conversion force at t = 0).
+ * LB_EGEOM if it overlaps a wall or another body or is too large for the
+ * box; LB_ESTATE after the first step. At most 253 bodies.               */
+int lb_add_squirmer(lb_sim *s, const lb_squirmer *sq, int *id);
+
+/* Enqueue nsteps time steps on the handle's stream.  Each step: geometry at
+ * the current body positions, cell conversion, stream with bounce-back and
+ * momentum exchange, TRT collision, force/torque reduction and rigid-body
+ * update (WCA included).                                                   */
+int lb_step(lb_sim *s, int nsteps);
+
+/* Advance several independent handles by nsteps each.  Every handle runs
+ * on its own stream and gives the same result it would give alone.        */
+int lb_step_batch(lb_sim *const *sims, int n, int nsteps);
+
+/* Block until the handle's queued work is done; reports device errors.   */
+int lb_sync(lb_sim *s);
+
+/* Density, velocity (u[k*N + c]) and owner (0 fluid, id+1 body, 255 wall;
+ * may be NULL) at the current time, FP64 host buffers of N, 3N and N.
+ * Solid cells get rho = 0 and u = 0.  u = sum f c / rho (with a body force
+ * g: (sum f c - g/2)/rho, the half-step velocity).                          */
+int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner);
+
+/* Hydrodynamic force and torque on body id from the last completed step:
+ * momentum exchange eqs. (bbforce), (bbtorque) plus conversion eq.
+ * (consforce).  These are the values the integrator used, minus WCA.       */
+int lb_force_torque(lb_sim *s, int id, double F[3], double T[3]);
+
+/* Same, split: momentum exchange (Fbb, Tbb) and conversion (Fc, Tc).       */
+int lb_force_parts(lb_sim *s, int id, double Fbb[3], double Tbb[3], double Fc[3], double Tc[3]);
+
+/* FP64 rigid-body state of body id after the last completed step; Fwca is
+ * the WCA force of that step. Any pointer may be NULL.                     */
+int lb_body_state(lb_sim *s, int id, double pos[3], double e[3], double v[3], double w[3],
+                  double Fwca[3]);
+
+/* The current boundary-link set {(c, i, o) : cell c fluid and cell
+ * c - c_i solid with owner o}, sorted by (c, i).  If cap < count, nothing
+ * is copied, *n receives the count and LB_EINVAL is returned.              */
+int lb_links(lb_sim *s, uint32_t *cell, uint8_t *dir, uint8_t *owner, size_t cap, size_t *n);
+
+/* Populations f_i (absolute, FP64, canonical order, f[i*N + c]); solid
+ * cells read 0 and are ignored on write.  Writing replaces the fluid state. */
+int lb_read_populations(lb_sim *s, double *f);
+int lb_write_populations(lb_sim *s, const double *f);
+
+/* FP64 total mass sum f and momentum sum f c over fluid cells.            */
+int lb_audit(lb_sim *s, double *mass, double P[3]);
+
+/* Number of fluid cells and of completed steps.                           */
+int lb_info(lb_sim *s, uint64_t *n_fluid, int64_t *steps);
+
+/* Checkpoint: the complete state (populations in storage format, cell
+ * owners, bodies, step count) as an opaque byte blob. lb_state_size gives
+ * its size; lb_load_state accepts only a blob from a handle created with
+ * the same lb_params and resumes bit for bit.                              */
+int lb_state_size(lb_sim *s, size_t *bytes);
+int lb_save_state(lb_sim *s, void *buf, size_t bytes);
+int lb_load_state(lb_sim *s, const void *buf, size_t bytes);
+
+/* Kernel timing for measurement: when enabled, HIP events bracket every
+ * launch of the fused stream-collide kernel; lb_kernel_time returns the
+ * summed duration (ms) and launch count since it was enabled.             */
+int lb_kernel_timing(lb_sim *s, int enable);
+int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches);
+
+int lb_destroy(lb_sim *s);
+const char *lb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBSQ_H */

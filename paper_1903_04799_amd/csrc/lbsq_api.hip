@@ -1,0 +1,695 @@
+// lbsq_api.hip -- the C ABI of include/lbsq.h: handle life cycle, argument
+// validation, device memory, step scheduling and readout.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbsq.h"
+#include "lbsq_launch.h"
+
+using namespace lbsq;
+
+struct lb_sim {
+    lb_params p;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    StepArgs args{};
+    size_t esize = 4;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t *own = nullptr;
+    uint16_t *ev = nullptr;
+    DevBody *d_bodies = nullptr;
+    std::vector<DevBody> bodies;
+    int *d_lists = nullptr;  // all_ids | all_start | mov_ids | mov_start
+    int nmov = 0, nblk_all = 0, nblk_mov = 0;
+    double *d_part = nullptr;
+    size_t part_blocks = 0;
+    double *d_audit_part = nullptr, *d_audit_out = nullptr;
+    int *d_err = nullptr;
+    int64_t steps = 0;
+    bool started = false, need_classify = true;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+
+namespace {
+
+constexpr int NERR = 4;
+
+int nblocks(uint64_t n) { return int((n + BLOCK - 1) / BLOCK); }
+
+// population plane stride: whole 256-element groups plus one extra group, so
+// that the 19 planes do not start at the same offset modulo large powers of
+// two
+uint64_t plane_stride(uint64_t n) { return ((n + 255) / 256) * 256 + 256; }
+
+void *dev_alloc(lb_sim *s, size_t bytes)
+{
+    void *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    if (s->p.alloc) {
+        p = s->p.alloc(bytes, s->p.alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    return p;
+}
+
+void dev_free(lb_sim *s, void *p)
+{
+    if (!p) return;
+    if (s->p.free) s->p.free(p, s->p.alloc_ctx);
+    else (void)hipFree(p);
+}
+
+int body_half_width(double R) { return int(std::ceil(R)) + 4; }
+
+double wrap_pos(double p, int n)
+{
+    p = std::fmod(p, double(n));
+    if (p < 0.0) p += n;
+    if (p >= n) p -= n;
+    return p;
+}
+
+// Wait for the stream and turn device-side error flags into a status.
+int sync_check(lb_sim *s)
+{
+    (void)hipSetDevice(s->device);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
+    int err[NERR];
+    if (hipMemcpy(err, s->d_err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    if (err[0] || err[1] || err[2]) {
+        int zero[NERR] = {0, 0, 0, 0};
+        (void)hipMemcpy(s->d_err, zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (err[1]) return LB_ENAN;
+        return LB_EGEOM;
+    }
+    return LB_OK;
+}
+
+int rebuild_lists(lb_sim *s)
+{
+    const int nb = int(s->bodies.size());
+    std::vector<int> all_ids(nb), all_start(nb + 1), mov_ids, mov_start(1, 0);
+    all_start[0] = 0;
+    for (int b = 0; b < nb; ++b) {
+        all_ids[b] = b;
+        const int side = 2 * s->bodies[b].H + 1;
+        const int blk = nblocks(uint64_t(side) * side * side);
+        all_start[b + 1] = all_start[b] + blk;
+        if (s->bodies[b].mode != LB_FIXED) {
+            mov_ids.push_back(b);
+            mov_start.push_back(mov_start.back() + blk);
+        }
+    }
+    s->nmov = int(mov_ids.size());
+    s->nblk_all = all_start[nb];
+    s->nblk_mov = mov_start.back();
+    std::vector<int> packed;
+    packed.insert(packed.end(), all_ids.begin(), all_ids.end());
+    packed.insert(packed.end(), all_start.begin(), all_start.end());
+    packed.insert(packed.end(), mov_ids.begin(), mov_ids.end());
+    packed.insert(packed.end(), mov_start.begin(), mov_start.end());
+    if (hipMemcpy(s->d_lists, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return LB_EDEVICE;
+    if (size_t(s->nblk_all) > s->part_blocks) {
+        dev_free(s, s->d_part);
+        s->d_part = static_cast<double *>(dev_alloc(s, size_t(s->nblk_all) * 12 * sizeof(double)));
+        if (!s->d_part) return LB_ENOMEM;
+        s->part_blocks = size_t(s->nblk_all);
+    }
+    return LB_OK;
+}
+
+void fill_launch(lb_sim *s, StepLaunch &L)
+{
+    const int nb = int(s->bodies.size());
+    L.args = s->args;
+    L.A = s->f[s->cur];
+    L.B = s->f[1 - s->cur];
+    L.own = s->own;
+    L.ev = s->ev;
+    L.bodies = s->d_bodies;
+    L.nbody = nb;
+    L.all_ids = s->d_lists;
+    L.all_start = s->d_lists + nb;
+    L.mov_ids = s->d_lists + 2 * nb + 1;
+    L.mov_start = s->d_lists + 2 * nb + 1 + s->nmov;
+    L.nmov = s->nmov;
+    L.nblk_mov = s->nblk_mov;
+    L.nblk_all = s->nblk_all;
+    L.part = s->d_part;
+    L.audit_part = s->d_audit_part;
+    L.audit_out = s->d_audit_out;
+    L.err = s->d_err;
+    L.wca_sigma = s->p.wca_sigma;
+    L.wca_eps = s->p.wca_eps;
+    L.audit = false;
+    L.ev_start = L.ev_stop = nullptr;
+    L.stream = s->stream;
+}
+
+int pull_bodies(lb_sim *s)
+{
+    if (s->bodies.empty()) return LB_OK;
+    if (hipMemcpy(s->bodies.data(), s->d_bodies, s->bodies.size() * sizeof(DevBody), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return LB_EDEVICE;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_strerror(int code)
+{
+    switch (code) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "device allocation failed";
+    case LB_EDEVICE: return "HIP runtime error";
+    case LB_EGEOM: return "invalid geometry (overlap, body too large, or a body moved a cell or more in a step)";
+    case LB_ESTATE: return "call not allowed in the current state";
+    case LB_ENAN: return "non-finite populations detected";
+    case LB_EBUDGET: return "memory budget exceeded";
+    default: return "unknown error";
+    }
+}
+
+int lb_destroy(lb_sim *s)
+{
+    if (!s) return LB_EINVAL;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &e : s->evs) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    dev_free(s, s->f[0]);
+    dev_free(s, s->f[1]);
+    dev_free(s, s->own);
+    dev_free(s, s->ev);
+    dev_free(s, s->d_bodies);
+    dev_free(s, s->d_lists);
+    dev_free(s, s->d_part);
+    dev_free(s, s->d_audit_part);
+    dev_free(s, s->d_audit_out);
+    dev_free(s, s->d_err);
+    delete s;
+    return LB_OK;
+}
+
+int lb_create(const lb_params *p, lb_sim **out)
+{
+    if (!p || !out) return LB_EINVAL;
+    *out = nullptr;
+    if (p->nx < 4 || p->ny < 4 || p->nz < 4) return LB_EINVAL;
+    const uint64_t n = uint64_t(p->nx) * p->ny * p->nz;
+    if (n >= (uint64_t(1) << 32)) return LB_EINVAL;
+    if (!(p->nu > 0.0) || !(p->magic > 0.0) || !(p->rho0 > 0.0)) return LB_EINVAL;
+    if (p->storage < 0 || p->storage > 2 || p->scale_log2 < 0 || p->scale_log2 > 20 || p->audit_every < 0)
+        return LB_EINVAL;
+    const double le = 1.0 / (3.0 * p->nu + 0.5);
+    const double lo = 1.0 / (p->magic / (1.0 / le - 0.5) + 0.5);
+    if (!(le > 0.0 && le < 2.0 && lo > 0.0 && lo < 2.0)) return LB_EINVAL;
+    if (!(p->wca_sigma > 0.0) || p->wca_eps < 0.0) return LB_EINVAL;
+    if ((p->alloc == nullptr) != (p->free == nullptr)) return LB_EINVAL;
+
+    lb_sim *s = new (std::nothrow) lb_sim();
+    if (!s) return LB_ENOMEM;
+    s->p = *p;
+    (void)hipGetDevice(&s->device);
+    s->stream = static_cast<hipStream_t>(p->stream);
+    Box &bx = s->args.box;
+    bx.nx = p->nx;
+    bx.ny = p->ny;
+    bx.nz = p->nz;
+    bx.n = uint32_t(n);
+    bx.stride = plane_stride(n);
+    s->args.lam_e = float(le);
+    s->args.lam_o = float(lo);
+    s->args.rho0 = float(p->rho0);
+    s->args.rho0d = p->rho0;
+    for (int k = 0; k < 3; ++k) s->args.g[k] = float(p->g[k]);
+    s->args.scale = std::ldexp(1.0f, p->scale_log2);
+    s->args.inv_scale = std::ldexp(1.0f, -p->scale_log2);
+    s->esize = p->storage == LB_STORAGE_F32 ? 4 : 2;
+
+    const size_t fbytes = size_t(Q) * bx.stride * s->esize;
+    s->f[0] = dev_alloc(s, fbytes);
+    s->f[1] = dev_alloc(s, fbytes);
+    s->own = static_cast<uint8_t *>(dev_alloc(s, n));
+    s->ev = static_cast<uint16_t *>(dev_alloc(s, n * sizeof(uint16_t)));
+    s->d_bodies = static_cast<DevBody *>(dev_alloc(s, MAXB * sizeof(DevBody)));
+    s->d_lists = static_cast<int *>(dev_alloc(s, 4 * (MAXB + 1) * sizeof(int)));
+    s->d_audit_part = static_cast<double *>(dev_alloc(s, size_t(nblocks(n)) * 5 * sizeof(double)));
+    s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
+    s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
+    if (!s->f[0] || !s->f[1] || !s->own || !s->ev || !s->d_bodies || !s->d_lists || !s->d_audit_part ||
+        !s->d_audit_out || !s->d_err) {
+        lb_destroy(s);
+        return LB_ENOMEM;
+    }
+    hipError_t e = hipSuccess;
+    e = hipMemsetAsync(s->f[0], 0, fbytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->f[1], 0, fbytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->own, 0, n, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ev, 0, n * sizeof(uint16_t), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, NERR * sizeof(int), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        lb_destroy(s);
+        return LB_EDEVICE;
+    }
+    *out = s;
+    return LB_OK;
+}
+
+int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n)
+{
+    if (!s || !solid) return LB_EINVAL;
+    if (n != s->args.box.n) return LB_EINVAL;
+    if (s->started || !s->bodies.empty()) return LB_ESTATE;
+    std::vector<uint8_t> h(n);
+    for (size_t c = 0; c < n; ++c) h[c] = solid[c] ? OWN_WALL : OWN_FLUID;
+    (void)hipSetDevice(s->device);
+    if (hipMemcpy(s->own, h.data(), n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    s->need_classify = true;
+    return LB_OK;
+}
+
+int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
+{
+    if (!s || !q) return LB_EINVAL;
+    if (s->started) return LB_ESTATE;
+    if (int(s->bodies.size()) >= MAXB) return LB_EINVAL;
+    if (q->mode < LB_FREE || q->mode > LB_PRESCRIBED) return LB_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(q->pos[k]) || !std::isfinite(q->e[k]) || !std::isfinite(q->v[k]) ||
+            !std::isfinite(q->w[k]))
+            return LB_EINVAL;
+    if (!(q->R > 0.5) || !std::isfinite(q->B1) || !std::isfinite(q->beta)) return LB_EINVAL;
+    const double en = std::sqrt(q->e[0] * q->e[0] + q->e[1] * q->e[1] + q->e[2] * q->e[2]);
+    if (!(en > 0.0)) return LB_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!(std::fabs(q->v[k]) < 1.0)) return LB_EINVAL;
+    const Box &bx = s->args.box;
+    DevBody B;
+    std::memset(&B, 0, sizeof(B));
+    B.H = body_half_width(q->R);
+    const int side = 2 * B.H + 1;
+    if (side > std::min(bx.nx, std::min(bx.ny, bx.nz))) return LB_EGEOM;
+    const int n3[3] = {bx.nx, bx.ny, bx.nz};
+    for (int k = 0; k < 3; ++k) {
+        B.pos[k] = wrap_pos(q->pos[k], n3[k]);
+        B.e[k] = q->e[k] / en;
+        B.v[k] = q->v[k];
+        B.w[k] = q->w[k];
+    }
+    B.R = q->R;
+    B.B1 = q->B1;
+    B.beta = q->beta;
+    B.mode = q->mode;
+    const double rho_p = q->rho_p > 0.0 ? q->rho_p : s->p.rho0;
+    B.m = rho_p * 4.0 / 3.0 * M_PI * q->R * q->R * q->R;
+    B.I = 0.4 * B.m * q->R * q->R;
+    B.Rq = std::llrint(q->R * double(int64_t(1) << 20));
+    const int b = int(s->bodies.size());
+    (void)hipSetDevice(s->device);
+    if (hipMemcpy(s->d_bodies + b, &B, sizeof(B), hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    if (launch_body_cells(bx, s->d_bodies, b, side, s->own, 1, s->d_err, s->stream) != hipSuccess)
+        return LB_EDEVICE;
+    const int st = sync_check(s);
+    if (st == LB_EGEOM) return LB_EGEOM;
+    if (st != LB_OK) return st;
+    if (launch_body_cells(bx, s->d_bodies, b, side, s->own, 0, s->d_err, s->stream) != hipSuccess)
+        return LB_EDEVICE;
+    s->bodies.push_back(B);
+    const int rc = rebuild_lists(s);
+    if (rc != LB_OK) return rc;
+    s->need_classify = true;
+    if (id) *id = b;
+    return sync_check(s);
+}
+
+int lb_step(lb_sim *s, int nsteps)
+{
+    if (!s || nsteps < 0) return LB_EINVAL;
+    (void)hipSetDevice(s->device);
+    if (s->need_classify) {
+        if (launch_classify(s->args.box, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
+        s->need_classify = false;
+    }
+    s->started = true;
+    for (int t = 0; t < nsteps; ++t) {
+        StepLaunch L;
+        fill_launch(s, L);
+        L.audit = s->p.audit_every > 0 && ((s->steps + 1) % s->p.audit_every == 0);
+        if (s->timing) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return LB_EDEVICE;
+            s->evs.emplace_back(a, b);
+            L.ev_start = a;
+            L.ev_stop = b;
+        }
+        if (launch_step(s->p.storage, L) != hipSuccess) return LB_EDEVICE;
+        s->cur ^= 1;
+        s->steps++;
+    }
+    return LB_OK;
+}
+
+int lb_step_batch(lb_sim *const *sims, int n, int nsteps)
+{
+    if ((!sims && n > 0) || n < 0 || nsteps < 0) return LB_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (!sims[k]) return LB_EINVAL;
+    for (int k = 0; k < n; ++k) {
+        const int rc = lb_step(sims[k], nsteps);
+        if (rc != LB_OK) return rc;
+    }
+    return LB_OK;
+}
+
+int lb_sync(lb_sim *s)
+{
+    if (!s) return LB_EINVAL;
+    return sync_check(s);
+}
+
+int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
+{
+    if (!s || !rho || !u) return LB_EINVAL;
+    const int st = sync_check(s);
+    if (st != LB_OK) return st;
+    const uint32_t n = s->args.box.n;
+    double *d_rho = static_cast<double *>(dev_alloc(s, size_t(n) * sizeof(double)));
+    double *d_u = static_cast<double *>(dev_alloc(s, size_t(n) * 3 * sizeof(double)));
+    uint8_t *d_o = static_cast<uint8_t *>(dev_alloc(s, n));
+    int rc = LB_OK;
+    if (!d_rho || !d_u || !d_o) rc = LB_ENOMEM;
+    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f[s->cur], s->own, d_rho, d_u, d_o, s->stream) !=
+                           hipSuccess)
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LB_EDEVICE;
+    if (rc == LB_OK && hipMemcpy(rho, d_rho, size_t(n) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && hipMemcpy(u, d_u, size_t(n) * 3 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && owner && hipMemcpy(owner, d_o, n, hipMemcpyDeviceToHost) != hipSuccess) rc = LB_EDEVICE;
+    dev_free(s, d_rho);
+    dev_free(s, d_u);
+    dev_free(s, d_o);
+    return rc;
+}
+
+int lb_force_parts(lb_sim *s, int id, double Fbb[3], double Tbb[3], double Fc[3], double Tc[3])
+{
+    if (!s || id < 0 || id >= int(s->bodies.size())) return LB_EINVAL;
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    st = pull_bodies(s);
+    if (st != LB_OK) return st;
+    const DevBody &B = s->bodies[id];
+    for (int k = 0; k < 3; ++k) {
+        if (Fbb) Fbb[k] = B.Fbb[k];
+        if (Tbb) Tbb[k] = B.Tbb[k];
+        if (Fc) Fc[k] = B.Fc[k];
+        if (Tc) Tc[k] = B.Tc[k];
+    }
+    return LB_OK;
+}
+
+int lb_force_torque(lb_sim *s, int id, double F[3], double T[3])
+{
+    if (!F || !T) return LB_EINVAL;
+    double fb[3], tb[3], fc[3], tc[3];
+    const int st = lb_force_parts(s, id, fb, tb, fc, tc);
+    if (st != LB_OK) return st;
+    for (int k = 0; k < 3; ++k) {
+        F[k] = fb[k] + fc[k];
+        T[k] = tb[k] + tc[k];
+    }
+    return LB_OK;
+}
+
+int lb_body_state(lb_sim *s, int id, double pos[3], double e[3], double v[3], double w[3], double Fwca[3])
+{
+    if (!s || id < 0 || id >= int(s->bodies.size())) return LB_EINVAL;
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    st = pull_bodies(s);
+    if (st != LB_OK) return st;
+    const DevBody &B = s->bodies[id];
+    for (int k = 0; k < 3; ++k) {
+        if (pos) pos[k] = B.pos[k];
+        if (e) e[k] = B.e[k];
+        if (v) v[k] = B.v[k];
+        if (w) w[k] = B.w[k];
+        if (Fwca) Fwca[k] = B.Fwca[k];
+    }
+    return LB_OK;
+}
+
+int lb_links(lb_sim *s, uint32_t *cell, uint8_t *dir, uint8_t *owner, size_t cap, size_t *n)
+{
+    if (!s || !n) return LB_EINVAL;
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    const Box &bx = s->args.box;
+    (void)hipSetDevice(s->device);
+    if (s->need_classify) {
+        if (launch_classify(bx, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
+        s->need_classify = false;
+    }
+    uint32_t *d_mask = static_cast<uint32_t *>(dev_alloc(s, size_t(bx.n) * sizeof(uint32_t)));
+    if (!d_mask) return LB_ENOMEM;
+    std::vector<uint32_t> mask(bx.n);
+    std::vector<uint8_t> own(bx.n);
+    int rc = LB_OK;
+    if (launch_link_mask(bx, s->own, d_mask, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess ||
+        hipMemcpy(mask.data(), d_mask, size_t(bx.n) * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(own.data(), s->own, bx.n, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = LB_EDEVICE;
+    dev_free(s, d_mask);
+    if (rc != LB_OK) return rc;
+    size_t cnt = 0;
+    for (uint32_t c = 0; c < bx.n; ++c) cnt += size_t(__builtin_popcount(mask[c]));
+    *n = cnt;
+    if (cnt > cap) return LB_EINVAL;
+    if (cnt && (!cell || !dir || !owner)) return LB_EINVAL;
+    size_t k = 0;
+    for (uint32_t c = 0; c < bx.n; ++c) {
+        const uint32_t m = mask[c];
+        if (!m) continue;
+        const int x = c % bx.nx, y = (c / bx.nx) % bx.ny, z = c / (uint32_t(bx.nx) * bx.ny);
+        for (int i = 1; i < Q; ++i) {
+            if (!(m & (1u << i))) continue;
+            const int sx = (x - cx(i) + bx.nx) % bx.nx, sy = (y - cy(i) + bx.ny) % bx.ny,
+                      sz = (z - cz(i) + bx.nz) % bx.nz;
+            cell[k] = c;
+            dir[k] = uint8_t(i);
+            owner[k] = own[uint32_t(sx) + uint32_t(bx.nx) * (uint32_t(sy) + uint32_t(bx.ny) * uint32_t(sz))];
+            ++k;
+        }
+    }
+    return LB_OK;
+}
+
+int lb_read_populations(lb_sim *s, double *f)
+{
+    if (!s || !f) return LB_EINVAL;
+    const int st = sync_check(s);
+    if (st != LB_OK) return st;
+    const uint32_t n = s->args.box.n;
+    double *buf = static_cast<double *>(dev_alloc(s, size_t(n) * sizeof(double)));
+    if (!buf) return LB_ENOMEM;
+    int rc = LB_OK;
+    for (int i = 0; i < Q && rc == LB_OK; ++i) {
+        if (launch_plane(s->p.storage, s->args, s->f[s->cur], s->own, i, buf, 1, s->stream) != hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess ||
+            hipMemcpy(f + size_t(i) * n, buf, size_t(n) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = LB_EDEVICE;
+    }
+    dev_free(s, buf);
+    return rc;
+}
+
+int lb_write_populations(lb_sim *s, const double *f)
+{
+    if (!s || !f) return LB_EINVAL;
+    const int st = sync_check(s);
+    if (st != LB_OK) return st;
+    const uint32_t n = s->args.box.n;
+    double *buf = static_cast<double *>(dev_alloc(s, size_t(n) * sizeof(double)));
+    if (!buf) return LB_ENOMEM;
+    int rc = LB_OK;
+    for (int i = 0; i < Q && rc == LB_OK; ++i) {
+        if (hipMemcpy(buf, f + size_t(i) * n, size_t(n) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            launch_plane(s->p.storage, s->args, s->f[s->cur], s->own, i, buf, 0, s->stream) != hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess)
+            rc = LB_EDEVICE;
+    }
+    dev_free(s, buf);
+    return rc;
+}
+
+static int audit_now(lb_sim *s, double out[5])
+{
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    if (launch_audit(s->p.storage, s->args, s->f[s->cur], s->own, s->d_audit_part, s->d_audit_out, s->d_err,
+                     s->stream) != hipSuccess)
+        return LB_EDEVICE;
+    st = sync_check(s);
+    if (st != LB_OK) return st;
+    if (hipMemcpy(out, s->d_audit_out, 5 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    return LB_OK;
+}
+
+int lb_audit(lb_sim *s, double *mass, double P[3])
+{
+    if (!s || !mass || !P) return LB_EINVAL;
+    double a[5];
+    const int st = audit_now(s, a);
+    if (st != LB_OK) return st;
+    *mass = s->p.rho0 * a[4] + a[0];
+    for (int k = 0; k < 3; ++k) P[k] = a[1 + k];
+    return LB_OK;
+}
+
+int lb_info(lb_sim *s, uint64_t *n_fluid, int64_t *steps)
+{
+    if (!s) return LB_EINVAL;
+    if (n_fluid) {
+        double a[5];
+        const int st = audit_now(s, a);
+        if (st != LB_OK) return st;
+        *n_fluid = uint64_t(a[4]);
+    }
+    if (steps) *steps = s->steps;
+    return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint blob: header, populations (storage format), owners, bodies
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t nx, ny, nz, storage, scale_log2, nbody;
+    int64_t steps;
+    uint64_t pop_bytes;
+};
+
+static constexpr uint64_t STATE_MAGIC = 0x31717362'6c62ull;
+
+int lb_state_size(lb_sim *s, size_t *bytes)
+{
+    if (!s || !bytes) return LB_EINVAL;
+    *bytes = sizeof(StateHeader) + size_t(Q) * s->args.box.stride * s->esize + s->args.box.n +
+             MAXB * sizeof(DevBody);
+    return LB_OK;
+}
+
+int lb_save_state(lb_sim *s, void *buf, size_t bytes)
+{
+    size_t need = 0;
+    if (!buf || lb_state_size(s, &need) != LB_OK || bytes < need) return LB_EINVAL;
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    st = pull_bodies(s);
+    if (st != LB_OK) return st;
+    if (s->need_classify) {
+        if (launch_classify(s->args.box, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
+        s->need_classify = false;
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
+    }
+    StateHeader h{STATE_MAGIC, s->p.nx, s->p.ny, s->p.nz, s->p.storage, s->p.scale_log2,
+                  int32_t(s->bodies.size()), s->steps, uint64_t(Q) * s->args.box.stride * s->esize};
+    char *p = static_cast<char *>(buf);
+    std::memset(p, 0, need);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    if (hipMemcpy(p, s->f[s->cur], h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    p += h.pop_bytes;
+    if (hipMemcpy(p, s->own, s->args.box.n, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    p += s->args.box.n;
+    if (!s->bodies.empty()) std::memcpy(p, s->bodies.data(), s->bodies.size() * sizeof(DevBody));
+    return LB_OK;
+}
+
+int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
+{
+    size_t need = 0;
+    if (!buf || lb_state_size(s, &need) != LB_OK || bytes < need) return LB_EINVAL;
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (h.magic != STATE_MAGIC || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
+        h.storage != s->p.storage || h.scale_log2 != s->p.scale_log2 || h.nbody < 0 || h.nbody > MAXB ||
+        h.pop_bytes != uint64_t(Q) * s->args.box.stride * s->esize)
+        return LB_EINVAL;
+    int st = sync_check(s);
+    if (st != LB_OK) return st;
+    const char *p = static_cast<const char *>(buf) + sizeof(h);
+    if (hipMemcpy(s->f[s->cur], p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    p += h.pop_bytes;
+    if (hipMemcpy(s->own, p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    p += s->args.box.n;
+    s->bodies.assign(h.nbody, DevBody{});
+    if (h.nbody) {
+        std::memcpy(s->bodies.data(), p, size_t(h.nbody) * sizeof(DevBody));
+        if (hipMemcpy(s->d_bodies, s->bodies.data(), size_t(h.nbody) * sizeof(DevBody), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return LB_EDEVICE;
+    }
+    st = rebuild_lists(s);
+    if (st != LB_OK) return st;
+    s->steps = h.steps;
+    s->started = true;
+    s->need_classify = false;
+    return sync_check(s);
+}
+
+int lb_kernel_timing(lb_sim *s, int enable)
+{
+    if (!s) return LB_EINVAL;
+    const int st = sync_check(s);
+    for (auto &e : s->evs) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    s->evs.clear();
+    s->ms = 0.0;
+    s->launches = 0;
+    s->timing = enable != 0;
+    return st;
+}
+
+int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches)
+{
+    if (!s || !ms || !launches) return LB_EINVAL;
+    const int st = sync_check(s);
+    if (st != LB_OK) return st;
+    for (auto &e : s->evs) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, e.first, e.second) != hipSuccess) return LB_EDEVICE;
+        s->ms += t;
+        s->launches++;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    s->evs.clear();
+    *ms = s->ms;
+    *launches = s->launches;
+    return LB_OK;
+}
+
+}  // extern "C"

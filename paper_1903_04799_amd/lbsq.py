@@ -1,0 +1,315 @@
+"""ctypes binding of ``liblbsq.so`` (the C ABI in ``include/lbsq.h``).
+
+Argument marshalling only: every step of the lattice Boltzmann squirmer path
+runs in the library's gfx950 kernels.  PyTorch, when present, supplies the
+device memory (through the allocator callbacks of ``lb_params``) and the HIP
+stream; nothing here computes.
+
+The library must be built (``python -m paper_1903_04799_amd.build``); there
+is no fallback: loading fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "liblbsq.so"
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EGEOM, LB_ESTATE, LB_ENAN, LB_EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+MODES = {"free": 0, "fixed": 1, "prescribed": 2}
+Q = 19
+
+EXPORTED = [
+    "lb_create", "lb_set_static_mask", "lb_add_squirmer", "lb_step", "lb_step_batch", "lb_sync",
+    "lb_read_fields", "lb_force_torque", "lb_force_parts", "lb_body_state", "lb_links",
+    "lb_read_populations", "lb_write_populations", "lb_audit", "lb_info", "lb_state_size",
+    "lb_save_state", "lb_load_state", "lb_kernel_timing", "lb_kernel_time", "lb_destroy",
+    "lb_strerror",
+]
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class LbParams(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("nu", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
+                ("storage", C.c_int), ("scale_log2", C.c_int),
+                ("wca_sigma", C.c_double), ("wca_eps", C.c_double),
+                ("g", C.c_double * 3), ("audit_every", C.c_int),
+                ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class LbSquirmer(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("e", C.c_double * 3), ("R", C.c_double),
+                ("B1", C.c_double), ("beta", C.c_double), ("mode", C.c_int),
+                ("v", C.c_double * 3), ("w", C.c_double * 3), ("rho_p", C.c_double)]
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise ImportError("liblbsq.so not built: run `python -m paper_1903_04799_amd.build` "
+                          "(expected at %s)" % LIB_PATH)
+    L = C.CDLL(str(LIB_PATH))
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    sig = {
+        "lb_create": [C.POINTER(LbParams), C.POINTER(vp)],
+        "lb_set_static_mask": [vp, vp, C.c_size_t],
+        "lb_add_squirmer": [vp, C.POINTER(LbSquirmer), C.POINTER(ip)],
+        "lb_step": [vp, ip],
+        "lb_step_batch": [C.POINTER(vp), ip, ip],
+        "lb_sync": [vp],
+        "lb_read_fields": [vp, dp, dp, vp],
+        "lb_force_torque": [vp, ip, dp, dp],
+        "lb_force_parts": [vp, ip, dp, dp, dp, dp],
+        "lb_body_state": [vp, ip, dp, dp, dp, dp, dp],
+        "lb_links": [vp, vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)],
+        "lb_read_populations": [vp, dp],
+        "lb_write_populations": [vp, dp],
+        "lb_audit": [vp, dp, dp],
+        "lb_info": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)],
+        "lb_state_size": [vp, C.POINTER(C.c_size_t)],
+        "lb_save_state": [vp, vp, C.c_size_t],
+        "lb_load_state": [vp, vp, C.c_size_t],
+        "lb_kernel_timing": [vp, ip],
+        "lb_kernel_time": [vp, dp, C.POINTER(C.c_int64)],
+        "lb_destroy": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.lb_strerror.argtypes = [C.c_int]
+    L.lb_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code):
+    return load().lb_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != LB_OK:
+        raise LBError(rc, what)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class _TorchMemory:
+    """Device allocator callbacks backed by torch's caching allocator."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.blocks = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        except Exception:
+            return None
+        self.blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, ctx):
+        self.blocks.pop(ptr, None)
+
+
+def _torch_cuda():
+    try:
+        import torch
+        return torch if torch.cuda.is_available() else None
+    except Exception:
+        return None
+
+
+class Sim:
+    """One periodic D3Q19 box with squirmers, resident on the GPU."""
+
+    def __init__(self, shape, nu=1.0 / 6.0, magic=3.0 / 16.0, rho0=1.0, storage="f32",
+                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, g=(0.0, 0.0, 0.0), audit_every=0,
+                 stream=None, torch_memory=True):
+        L = load()
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self.n = nx * ny * nz
+        p = LbParams()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.nu, p.magic, p.rho0 = float(nu), float(magic), float(rho0)
+        p.storage = STORAGE[storage]
+        if scale_log2 is None:
+            scale_log2 = 14 if storage == "f16" else 0
+        p.scale_log2 = int(scale_log2)
+        p.wca_sigma, p.wca_eps = float(wca_sigma), float(wca_eps)
+        p.g = (C.c_double * 3)(*[float(x) for x in g])
+        p.audit_every = int(audit_every)
+        self._mem = None
+        torch = _torch_cuda()
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        p.stream = stream
+        if torch_memory and torch is not None:
+            self._mem = _TorchMemory(torch.device("cuda", torch.cuda.current_device()))
+            p.alloc, p.free = self._mem.alloc_cb, self._mem.free_cb
+        self.params = p
+        self.storage = storage
+        h = C.c_void_p()
+        _check(L.lb_create(C.byref(p), C.byref(h)), "lb_create")
+        self.h = h
+        self.nbody = 0
+
+    # -- life cycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            load().lb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- set-up ------------------------------------------------------------
+    def set_static_mask(self, solid):
+        m = np.ascontiguousarray(np.asarray(solid).reshape(-1) != 0, dtype=np.uint8)
+        _check(load().lb_set_static_mask(self.h, m.ctypes.data, m.size), "lb_set_static_mask")
+
+    def add_squirmer(self, pos, e=(1.0, 0.0, 0.0), R=4.0, B1=0.0, beta=0.0, mode="free",
+                     v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), rho_p=0.0):
+        q = LbSquirmer()
+        q.pos = (C.c_double * 3)(*map(float, pos))
+        q.e = (C.c_double * 3)(*map(float, e))
+        q.R, q.B1, q.beta = float(R), float(B1), float(beta)
+        q.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        q.v = (C.c_double * 3)(*map(float, v))
+        q.w = (C.c_double * 3)(*map(float, w))
+        q.rho_p = float(rho_p)
+        i = C.c_int(-1)
+        _check(load().lb_add_squirmer(self.h, C.byref(q), C.byref(i)), "lb_add_squirmer")
+        self.nbody += 1
+        return i.value
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n=1):
+        _check(load().lb_step(self.h, int(n)), "lb_step")
+
+    def sync(self):
+        _check(load().lb_sync(self.h), "lb_sync")
+
+    # -- readout -----------------------------------------------------------
+    def fields(self):
+        nx, ny, nz = self.shape
+        rho = np.empty(self.n)
+        u = np.empty(3 * self.n)
+        own = np.empty(self.n, dtype=np.uint8)
+        _check(load().lb_read_fields(self.h, _dptr(rho), _dptr(u), own.ctypes.data), "lb_read_fields")
+        return rho.reshape(nz, ny, nx), u.reshape(3, nz, ny, nx), own.reshape(nz, ny, nx)
+
+    def force_torque(self, i=0):
+        F, T = np.empty(3), np.empty(3)
+        _check(load().lb_force_torque(self.h, int(i), _dptr(F), _dptr(T)), "lb_force_torque")
+        return F, T
+
+    def force_parts(self, i=0):
+        a = [np.empty(3) for _ in range(4)]
+        _check(load().lb_force_parts(self.h, int(i), *[_dptr(x) for x in a]), "lb_force_parts")
+        return dict(zip(("Fbb", "Tbb", "Fc", "Tc"), a))
+
+    def body(self, i=0):
+        a = [np.empty(3) for _ in range(5)]
+        _check(load().lb_body_state(self.h, int(i), *[_dptr(x) for x in a]), "lb_body_state")
+        return dict(zip(("pos", "e", "v", "w", "Fwca"), a))
+
+    def links(self):
+        L = load()
+        n = C.c_size_t(0)
+        rc = L.lb_links(self.h, None, None, None, 0, C.byref(n))
+        if rc not in (LB_OK, LB_EINVAL):
+            _check(rc, "lb_links")
+        cnt = n.value
+        cell = np.empty(cnt, dtype=np.uint32)
+        d = np.empty(cnt, dtype=np.uint8)
+        o = np.empty(cnt, dtype=np.uint8)
+        _check(L.lb_links(self.h, cell.ctypes.data, d.ctypes.data, o.ctypes.data, cnt, C.byref(n)),
+               "lb_links")
+        return cell, d, o
+
+    def populations(self):
+        nx, ny, nz = self.shape
+        f = np.empty(Q * self.n)
+        _check(load().lb_read_populations(self.h, _dptr(f)), "lb_read_populations")
+        return f.reshape(Q, nz, ny, nx)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        if f.size != Q * self.n:
+            raise ValueError("populations must have 19*N entries")
+        _check(load().lb_write_populations(self.h, _dptr(f)), "lb_write_populations")
+
+    def audit(self):
+        m = C.c_double()
+        P = np.empty(3)
+        _check(load().lb_audit(self.h, C.byref(m), _dptr(P)), "lb_audit")
+        return m.value, P
+
+    def info(self):
+        nf, st = C.c_uint64(), C.c_int64()
+        _check(load().lb_info(self.h, C.byref(nf), C.byref(st)), "lb_info")
+        return {"n_fluid": nf.value, "steps": st.value}
+
+    # -- checkpoint --------------------------------------------------------
+    def save_state(self):
+        n = C.c_size_t()
+        _check(load().lb_state_size(self.h, C.byref(n)), "lb_state_size")
+        buf = C.create_string_buffer(n.value)
+        _check(load().lb_save_state(self.h, buf, n.value), "lb_save_state")
+        return buf.raw
+
+    def load_state(self, blob):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(load().lb_load_state(self.h, buf, len(blob)), "lb_load_state")
+
+    # -- measurement ---------------------------------------------------------
+    def kernel_timing(self, enable=True):
+        _check(load().lb_kernel_timing(self.h, 1 if enable else 0), "lb_kernel_timing")
+
+    def kernel_time(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(load().lb_kernel_time(self.h, C.byref(ms), C.byref(n)), "lb_kernel_time")
+        return ms.value, n.value
+
+
+def step_batch(sims, nsteps):
+    arr = (C.c_void_p * len(sims))(*[s.h for s in sims])
+    _check(load().lb_step_batch(arr, len(sims), int(nsteps)), "lb_step_batch")

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the built library loads, exports every
+entry point that include/lbsq.h declares, and rejects bad arguments before
+touching the device.  No compute call is made, so these run without a GPU."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_1903_04799_amd import lbsq
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "lbsq.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbsq.load()
+    names = declared_functions()
+    assert "lb_create" in names and "lb_step" in names and "lb_force_torque" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(lbsq.EXPORTED) == names
+
+
+def test_strerror_names_every_code():
+    for code in range(0, -8, -1):
+        assert lbsq.strerror(code) and lbsq.strerror(code) != "unknown error"
+    assert lbsq.strerror(-99) == "unknown error"
+
+
+def _params(**kw):
+    p = lbsq.LbParams()
+    p.nx = p.ny = p.nz = 16
+    p.nu, p.magic, p.rho0 = 1 / 6, 3 / 16, 1.0
+    p.storage, p.scale_log2 = 0, 0
+    p.wca_sigma, p.wca_eps = 1.0, 0.01
+    p.audit_every = 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=3), dict(ny=0), dict(nz=-4), dict(nu=0.0), dict(nu=-1.0), dict(magic=0.0),
+    dict(rho0=0.0), dict(storage=3), dict(scale_log2=21), dict(scale_log2=-1),
+    dict(audit_every=-1), dict(wca_sigma=0.0), dict(wca_eps=-1.0),
+    dict(nx=2048, ny=2048, nz=1024),
+])
+def test_create_rejects_bad_parameters(kw):
+    L = lbsq.load()
+    h = C.c_void_p(123)
+    p = _params(**kw)
+    assert L.lb_create(C.byref(p), C.byref(h)) == lbsq.LB_EINVAL
+    assert h.value is None
+
+
+def test_null_arguments_rejected():
+    L = lbsq.load()
+    assert L.lb_create(None, None) == lbsq.LB_EINVAL
+    assert L.lb_step(None, 1) == lbsq.LB_EINVAL
+    assert L.lb_sync(None) == lbsq.LB_EINVAL
+    assert L.lb_destroy(None) == lbsq.LB_EINVAL
+    assert L.lb_step_batch(None, -1, 1) == lbsq.LB_EINVAL
+    assert L.lb_audit(None, None, None) == lbsq.LB_EINVAL

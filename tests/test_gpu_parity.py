@@ -1,0 +1,379 @@
+"""GPU parity: the gfx950 library against the FP64 oracle, through the C ABI.
+
+Tolerances (FP32 arithmetic on stored FP32 deviations):
+  - velocity: max_x |u_gpu - u_ref| / max_x |u_ref| <= 1e-5;
+  - density deviations: max |rho_gpu - rho_ref| <= 1e-9;
+  - force: |F_gpu - F_ref| <= 1e-5 of the Stokes drag scale 6 pi eta R U
+    (U the larger of the swim speed 2 B1 / 3 and the body speed).  The net
+    force on a swimmer tends to zero (self-propulsion is force-free), so the
+    net force itself is no scale for its error; torque likewise against
+    R times that scale;
+  - body positions: 1e-5 of the displacement;
+  - owners, link sets and conversion geometry: bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import scenes
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-5
+F_TOL = 1e-5
+
+
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_04799_amd import lbsq
+    return lbsq
+
+
+def note(msg):
+    print("[gpu-parity] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_pair(shape, bodies=(), mask=None, g=(0.0, 0.0, 0.0), storage="f32", f0=None, audit_every=0):
+    lbsq = gpu()
+    o = O.OracleSim(*shape, g=g)
+    s = lbsq.Sim(shape, storage=storage, g=g, audit_every=audit_every)
+    if mask is not None:
+        o.set_static_mask(mask)
+        s.set_static_mask(mask)
+    modes = {"free": O.FREE, "fixed": O.FIXED, "prescribed": O.PRESCRIBED}
+    for b in bodies:
+        b = dict(b)
+        mode = b.pop("mode", "free")
+        o.add_body(b["pos"], b.get("e", (1, 0, 0)), b["R"], B1=b.get("B1", 0.0), beta=b.get("beta", 0.0),
+                   mode=modes[mode], v=b.get("v", (0, 0, 0)), w=b.get("w", (0, 0, 0)))
+        s.add_squirmer(b["pos"], b.get("e", (1, 0, 0)), b["R"], B1=b.get("B1", 0.0), beta=b.get("beta", 0.0),
+                       mode=mode, v=b.get("v", (0, 0, 0)), w=b.get("w", (0, 0, 0)))
+    if f0 is not None:
+        o.set_populations(f0)
+        s.set_populations(f0)
+    return o, s
+
+
+def rel_u_err(s, o):
+    rho, u, own = s.fields()
+    rho_o, u_o, own_o = o.fields()
+    assert np.array_equal(own, own_o), "owner fields differ"
+    fl = own_o == 0
+    du = np.linalg.norm(u - u_o, axis=0)[fl].max()
+    ref = np.linalg.norm(u_o, axis=0)[fl].max()
+    drho = np.abs(rho - rho_o)[fl].max()
+    return du / ref, drho
+
+
+def drag_scale(specs, nu=1 / 6):
+    """6 pi eta R U of the largest body (eta = rho0 nu, rho0 = 1)."""
+    U = max(max(2 / 3 * abs(b.get("B1", 0.0)), np.linalg.norm(b.get("v", (0, 0, 0)))) for b in specs)
+    R = max(b["R"] for b in specs)
+    return 6 * np.pi * nu * R * max(U, 1e-4), R
+
+
+def check_bodies(s, o, specs, f_tol=F_TOL, pos_tol=1e-5, exact_pos=False):
+    fs, R = drag_scale(specs)
+    for i, spec in enumerate(specs):
+        b = o.body(i)
+        F, T = s.force_torque(i)
+        Fo = b["Fbb"] + b["Fc"]
+        To = b["Tbb"] + b["Tc"]
+        assert np.abs(F - Fo).max() <= f_tol * fs, (i, F, Fo)
+        assert np.abs(T - To).max() <= f_tol * fs * R, (i, T, To)
+        st = s.body(i)
+        if exact_pos:
+            assert np.array_equal(st["pos"], b["pos"])
+        else:
+            disp = np.abs(b["pos"] - np.asarray(spec["pos"])).max()
+            assert np.abs(st["pos"] - b["pos"]).max() <= pos_tol * max(disp, 1e-3), (i, st["pos"], b["pos"])
+
+
+def random_state(shape, seed, amp=1e-3):
+    _, w = O.lattice()
+    nx, ny, nz = shape
+    return w[:, None, None, None] * (1.0 + scenes.noise(seed, (19, nz, ny, nx), amp))
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(23, 19, 17), (64, 8, 6)])
+def test_periodic_fluid_random_state(shape):
+    note("periodic fluid %s" % (shape,))
+    f0 = random_state(shape, 3)
+    o, s = make_pair(shape, f0=f0)
+    for _ in range(3):
+        o.step(10)
+        s.step(10)
+        err, drho = rel_u_err(s, o)
+        assert err <= U_TOL and drho <= 1e-9, (err, drho)
+    fg, fo = s.populations(), o.populations()
+    assert np.abs(fg - fo).max() <= 1e-8
+
+
+def test_rest_state_is_bitwise_fixed_point():
+    note("rest state with a fixed no-slip sphere")
+    lbsq = gpu()
+    s = lbsq.Sim((24, 24, 24))
+    s.add_squirmer((12, 12, 12), (1, 0, 0), 5.0, B1=0.0, mode="fixed")
+    f0 = s.populations()
+    s.step(50)
+    f1 = s.populations()
+    assert np.array_equal(f0, f1)
+    # the force is a sum of O(1e3) link terms of size ~0.1 whose pressure
+    # parts cancel; what is left is FP64 round-off
+    F, T = s.force_torque(0)
+    assert np.abs(F).max() < 1e-13 and np.abs(T).max() < 1e-12
+
+
+def test_config_small_free_squirmer():
+    """32^3 box, R=4 neutral squirmer at the centre swimming along +x,
+    B1 = 1e-3, 200 steps (the oracle-size configuration)."""
+    note("32^3 R=4 beta=0 free, 200 steps")
+    shape = (32, 32, 32)
+    body = dict(pos=(16.0, 16.0, 16.0), e=(1, 0, 0), R=4.0, B1=1e-3, beta=0.0)
+    o, s = make_pair(shape, [body])
+    for _ in range(4):
+        o.step(50)
+        s.step(50)
+        err, drho = rel_u_err(s, o)
+        assert err <= U_TOL, err
+        check_bodies(s, o, [body])
+    m_g, P_g = s.audit()
+    m_o, P_o = o.audit()
+    assert abs(m_g - m_o) <= 1e-9 * m_o
+    assert np.abs(P_g - P_o).max() <= 1e-5 * np.abs(P_o).max()
+
+
+@pytest.mark.parametrize("beta", [-5.0, 5.0])
+def test_free_squirmer_tilted(beta):
+    note("tilted free squirmer beta=%g" % beta)
+    shape = (30, 26, 22)
+    e = scenes.unit_vector(np.random.default_rng(11))
+    body = dict(pos=(14.3, 12.9, 10.6), e=tuple(e), R=4.5, B1=2e-3, beta=beta)
+    o, s = make_pair(shape, [body])
+    o.step(120)
+    s.step(120)
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, [body])
+    assert np.abs(s.body(0)["e"] - o.body(0)["e"]).max() < 1e-7
+
+
+def test_prescribed_motion_geometry_bit_exact():
+    """A prescribed body crosses many cells: owners and the full link set
+    equal the oracle's bit for bit at every step; fields stay in tolerance."""
+    note("prescribed moving body, per-step link sets")
+    shape = (28, 24, 20)
+    body = dict(pos=(9.2, 11.7, 10.1), e=(0, 1, 0), R=3.7, B1=5e-3, beta=2.0, mode="prescribed",
+                v=(0.23, 0.07, -0.05), w=(0.0, 0.01, 0.02))
+    o, s = make_pair(shape, [body])
+    for t in range(25):
+        o.step(1)
+        s.step(1)
+        cg, dg, og = s.links()
+        co, do, oo = o.links()
+        assert np.array_equal(cg, co) and np.array_equal(dg, do) and np.array_equal(og, oo), t
+        assert np.array_equal(s.body(0)["pos"], o.body(0)["pos"])
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, [body], exact_pos=True)
+
+
+def test_two_squirmers_with_contact():
+    """Two free squirmers swimming at each other reach WCA contact."""
+    note("two squirmers, WCA")
+    shape = (40, 24, 24)
+    bodies = [dict(pos=(13.0, 12.0, 12.0), e=(1, 0, 0), R=4.0, B1=0.03, beta=1.0),
+              dict(pos=(23.5, 12.3, 12.1), e=(-1, 0.1, 0), R=4.0, B1=0.03, beta=-1.0)]
+    lbsq = gpu()
+    o = O.OracleSim(*shape, wca_sigma=1.0, wca_eps=0.01)
+    s = lbsq.Sim(shape, wca_sigma=1.0, wca_eps=0.01)
+    for b in bodies:
+        o.add_body(b["pos"], b["e"], b["R"], B1=b["B1"], beta=b["beta"])
+        s.add_squirmer(b["pos"], b["e"], b["R"], B1=b["B1"], beta=b["beta"])
+    wca_seen = False
+    for _ in range(6):
+        o.step(25)
+        s.step(25)
+        wca_seen |= np.abs(o.body(0)["Fwca"]).max() > 0
+        err, _ = rel_u_err(s, o)
+        assert err <= U_TOL, err
+        check_bodies(s, o, bodies)
+    assert wca_seen
+
+
+def test_tube_with_static_walls():
+    note("squirmer in a tube")
+    shape = (24, 24, 40)
+    mask = scenes.tube_mask(*shape, radius=9.0)
+    body = dict(pos=(12.0, 12.0, 20.0), e=(0, 0, 1), R=4.0, B1=2e-3, beta=3.0)
+    o, s = make_pair(shape, [body], mask=mask)
+    o.step(150)
+    s.step(150)
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, [body])
+    cg, dg, og = s.links()
+    co, do, oo = o.links()
+    assert np.array_equal(cg, co) and np.array_equal(dg, do) and np.array_equal(og, oo)
+
+
+def test_fixed_obstacle_and_squirmer():
+    note("fixed obstacle + squirmer")
+    shape = (40, 32, 32)
+    bodies = [dict(pos=(26.0, 16.0, 16.0), R=6.0, mode="fixed"),
+              dict(pos=(12.0, 18.5, 16.0), e=(1, 0, 0), R=4.0, B1=5e-3, beta=-3.0)]
+    o, s = make_pair(shape, bodies)
+    o.step(100)
+    s.step(100)
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, bodies)
+
+
+def test_symmetric_placement_no_lateral_force():
+    note("symmetry")
+    lbsq = gpu()
+    s = lbsq.Sim((24, 24, 24))
+    s.add_squirmer((12, 12, 12), (1, 0, 0), 4.0, B1=1e-3, beta=5.0)
+    s.step(6)
+    F, T = s.force_torque(0)
+    assert abs(F[0]) > 0
+    # FP32 round-off only: 1e-6 of the axial force (torque: times R)
+    assert abs(F[1]) < 1e-6 * abs(F[0]) and abs(F[2]) < 1e-6 * abs(F[0])
+    assert np.abs(T).max() < 1e-6 * 4.0 * abs(F[0])
+
+
+def test_poiseuille_body_force_hook():
+    note("Poiseuille (test body force)")
+    H, g = 8, 1e-4
+    shape = (4, H + 2, 4)
+    mask = np.zeros((4, H + 2, 4), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, H + 1, :] = 1
+    o, s = make_pair(shape, mask=mask, g=(g, 0.0, 0.0))
+    n = int(40 / ((1 / 6) * (np.pi / H) ** 2))
+    o.step(n)
+    s.step(n)
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    _, u, _ = s.fields()
+    yp = np.arange(1, H + 1) - 0.5
+    exact = g / (2 / 6) * yp * (H - yp)
+    assert np.abs(u[0, 0, 1:H + 1, 0] - exact).max() <= 1e-5 * exact.max()
+
+
+def test_determinism_and_checkpoint_resume():
+    note("determinism + checkpoint")
+    lbsq = gpu()
+    shape = (32, 28, 24)
+    spec = ((15.2, 13.9, 12.3), (0.6, 0.8, 0.0), 4.2)
+
+    def fresh():
+        s = lbsq.Sim(shape)
+        s.add_squirmer(spec[0], spec[1], spec[2], B1=0.01, beta=-2.0)
+        return s
+
+    a = fresh()
+    a.step(60)
+    blob = a.save_state()
+    a.step(60)
+    b = fresh()
+    b.step(120)
+    assert np.array_equal(a.populations(), b.populations())
+    c = fresh()
+    c.load_state(blob)
+    c.step(60)
+    assert np.array_equal(a.populations(), c.populations())
+    for k in ("pos", "e", "v", "w"):
+        assert np.array_equal(a.body(0)[k], c.body(0)[k])
+
+
+def test_fused_audit_runs_and_flags_nothing():
+    note("fused audit")
+    shape = (20, 20, 20)
+    o, s = make_pair(shape, [dict(pos=(10, 10, 10), R=4.0, B1=1e-3)], audit_every=5)
+    s.step(40)
+    o.step(40)
+    s.sync()
+    m_g, P_g = s.audit()
+    m_o, P_o = o.audit()
+    assert abs(m_g - m_o) <= 1e-9 * m_o and np.abs(P_g - P_o).max() <= 1e-5 * np.abs(P_o).max()
+
+
+def test_nan_is_reported():
+    note("NaN detection via the fused audit")
+    lbsq = gpu()
+    s = lbsq.Sim((16, 16, 16), audit_every=1)
+    f = s.populations()
+    f[3, 4, 5, 6] = np.nan
+    s.set_populations(f)
+    s.step(2)
+    with pytest.raises(lbsq.LBError) as ei:
+        s.sync()
+    assert ei.value.code == lbsq.LB_ENAN
+
+
+def test_error_paths():
+    note("error paths")
+    lbsq = gpu()
+    s = lbsq.Sim((24, 24, 24))
+    s.add_squirmer((8, 12, 12), (1, 0, 0), 4.0)
+    with pytest.raises(lbsq.LBError) as ei:
+        s.add_squirmer((12, 12, 12), (1, 0, 0), 4.0)  # overlaps
+    assert ei.value.code == lbsq.LB_EGEOM
+    with pytest.raises(lbsq.LBError) as ei:
+        s.add_squirmer((18, 12, 12), (0, 0, 0), 2.0)  # zero orientation
+    assert ei.value.code == lbsq.LB_EINVAL
+    with pytest.raises(lbsq.LBError) as ei:
+        s.set_static_mask(np.zeros(24 ** 3))  # after a body
+    assert ei.value.code == lbsq.LB_ESTATE
+    with pytest.raises(lbsq.LBError) as ei:
+        lbsq.Sim((16, 16, 16)).add_squirmer((8, 8, 8), (1, 0, 0), 6.0)  # box too small
+    assert ei.value.code == lbsq.LB_EGEOM
+    s.step(1)
+    with pytest.raises(lbsq.LBError) as ei:
+        s.add_squirmer((20, 20, 20), (1, 0, 0), 1.0)
+    assert ei.value.code == lbsq.LB_ESTATE
+
+
+@pytest.mark.parametrize("storage,l2_tol", [("f16", 1e-3), ("bf16", 2e-2)])
+def test_reduced_precision_storage(storage, l2_tol):
+    """FP16 (scale 2^14) and BF16 deviation storage: velocity-field L2 error
+    and swim velocity against the FP64 oracle."""
+    note("storage %s" % storage)
+    shape = (32, 32, 32)
+    body = dict(pos=(16.0, 16.0, 16.0), e=(1, 0, 0), R=4.0, B1=1e-3, beta=-3.0)
+    o, s = make_pair(shape, [body], storage=storage)
+    o.step(200)
+    s.step(200)
+    _, u, own = s.fields()
+    _, u_o, own_o = o.fields()
+    assert np.array_equal(own, own_o)
+    fl = own_o == 0
+    l2 = np.linalg.norm((u - u_o)[:, fl]) / np.linalg.norm(u_o[:, fl])
+    note("  %s velocity L2 error %.3e" % (storage, l2))
+    assert l2 <= l2_tol
+    vg, vo = s.body(0)["v"][0], o.body(0)["v"][0]
+    assert abs(vg - vo) <= 5e-3 * abs(vo) if storage == "f16" else abs(vg - vo) <= 5e-2 * abs(vo)
+
+
+@pytest.mark.slow
+def test_full_size_box_128_few_steps():
+    """128^3, R=8 pusher at the box centre (the FP32 benchmark workload),
+    a few steps compared field by field with the oracle."""
+    note("128^3 R=8 beta=-5, 4 steps")
+    shape = (128, 128, 128)
+    body = dict(pos=(64.0, 64.0, 64.0), e=(1, 0, 0), R=8.0, B1=1e-3, beta=-5.0)
+    o, s = make_pair(shape, [body])
+    o.step(4)
+    s.step(4)
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, [body])
