@@ -40,8 +40,12 @@
  *     levels, rho0 if none;
  *   - inside test in int64 fixed point with 2^-20 quanta, cell centres at
  *     i + 1/2, ties count as inside;
- *   - step order: geometry, conversion, stream + bounce-back + momentum
- *     exchange, collide, integrate;
+ *   - step order: stream + bounce-back + momentum exchange, collide,
+ *     integrate, then geometry at the new positions and cell conversion;
+ *     the conversion force enters the following integration (the same
+ *     sequence of operations as converting at the start of the next step;
+ *     the state between steps has cell owners that match the body
+ *     positions);
  *   - symplectic Euler: v first, then r with the new v; w then e rotated by
  *     the exact rotation of angle |w| about w; m = rho_p 4/3 pi R^3,
  *     I = 2/5 m R^2;
@@ -90,6 +94,7 @@ typedef struct {
     double R, B1, beta, rho_p, m, I;
     int mode;
     double Fbb[3], Tbb[3], Fc[3], Tc[3], Fwca[3], F[3], T[3];
+    double Fcn[3], Tcn[3]; /* conversion force/torque waiting for the next integration */
 } or_body;
 
 typedef struct {
@@ -490,26 +495,25 @@ static void push_conv(or_sim *s, int covered, size_t idx, uint8_t o)
     }
 }
 
-static void one_step(or_sim *s)
+/* Cell conversion after the bodies have moved: covered cells hand their
+ * momentum to the body, uncovered cells are refilled; the compensating force
+ * and torque (eq. (consforce)) are kept for the next integration. */
+static void convert_cells(or_sim *s)
 {
     const size_t n = s->n;
     double *f = s->f;
-
-    for (int b = 0; b < s->nbody; ++b) {
-        or_body *B = &s->body[b];
-        for (int k = 0; k < 3; ++k) B->Fbb[k] = B->Tbb[k] = B->Fc[k] = B->Tc[k] = B->Fwca[k] = 0.0;
-    }
-    s->st_link_mass = s->st_covered_mass = s->st_uncovered_mass = 0.0;
+    for (int b = 0; b < s->nbody; ++b)
+        for (int k = 0; k < 3; ++k) s->body[b].Fcn[k] = s->body[b].Tcn[k] = 0.0;
+    s->st_covered_mass = s->st_uncovered_mass = 0.0;
     s->st_ncovered = s->st_nuncovered = 0;
-    s->nlinks = 0;
     s->ncov = s->nunc = 0;
 
-    /* 1. geometry at r(t) */
+    /* geometry at the new positions r(t+1) */
     uint8_t *own_new = (uint8_t *)malloc(n);
     if (compute_owner(s, own_new)) s->geom_error = 1;
     memset(s->uncovered, 0, n);
 
-    /* 2. covered cells: fluid before, body now; their momentum goes to the body */
+    /* covered cells: fluid before, body now; their momentum goes to the body */
     for (size_t idx = 0; idx < n; ++idx) {
         uint8_t o_old = s->owner[idx], o_new = own_new[idx];
         if (is_fluid(o_old) && o_new != OWN_FLUID && o_new != OWN_WALL) {
@@ -526,8 +530,8 @@ static void one_step(or_sim *s)
             lever(s, B, x, y, z, d);
             cross(d, p, dxp);
             for (int k = 0; k < 3; ++k) {
-                B->Fc[k] += p[k];
-                B->Tc[k] += dxp[k];
+                B->Fcn[k] += p[k];
+                B->Tcn[k] += dxp[k];
             }
             s->st_covered_mass += cell_rho(s, f, idx);
             s->st_ncovered++;
@@ -543,7 +547,7 @@ static void one_step(or_sim *s)
         if (!is_fluid(s->owner[idx]) && !s->uncovered[idx])
             for (int i = 0; i < Q; ++i) f[i * n + idx] = 0.0;
 
-    /* 3. uncovered cells: refill with f^eq(mean neighbour density, v + w x d).
+    /* uncovered cells: refill with f^eq(mean neighbour density, v + w x d).
      * The densities are taken before any refill is written. */
     double *refill_rho = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     for (size_t idx = 0; idx < n; ++idx) {
@@ -578,8 +582,8 @@ static void one_step(or_sim *s)
         double p[3] = {rb * u[0], rb * u[1], rb * u[2]};
         cross(d, p, dxp);
         for (int k = 0; k < 3; ++k) {
-            B->Fc[k] -= p[k];
-            B->Tc[k] -= dxp[k];
+            B->Fcn[k] -= p[k];
+            B->Tcn[k] -= dxp[k];
         }
         s->st_uncovered_mass += rb;
         s->st_nuncovered++;
@@ -587,6 +591,19 @@ static void one_step(or_sim *s)
     }
     free(refill_rho);
     free(own_old);
+}
+
+static void one_step(or_sim *s)
+{
+    const size_t n = s->n;
+    double *f = s->f;
+
+    for (int b = 0; b < s->nbody; ++b) {
+        or_body *B = &s->body[b];
+        for (int k = 0; k < 3; ++k) B->Fbb[k] = B->Tbb[k] = B->Fwca[k] = 0.0;
+    }
+    s->st_link_mass = 0.0;
+    s->nlinks = 0;
 
     /* 4a. boundary links, momentum exchange and the wall mass term */
     for (size_t idx = 0; idx < n; ++idx) {
@@ -683,11 +700,14 @@ static void one_step(or_sim *s)
     for (int b = 0; b < s->nbody; ++b) {
         or_body *B = &s->body[b];
         for (int k = 0; k < 3; ++k) {
+            B->Fc[k] = B->Fcn[k];
+            B->Tc[k] = B->Tcn[k];
             B->F[k] = B->Fbb[k] + B->Fc[k] + B->Fwca[k];
             B->T[k] = B->Tbb[k] + B->Tc[k];
         }
         or_integrate(B->pos, B->e, B->v, B->w, B->F, B->T, B->m, B->I, B->mode, nn);
     }
+    convert_cells(s);
     s->step++;
 }
 
@@ -738,16 +758,19 @@ int or_set_populations(or_sim *s, const double *f)
     return 0;
 }
 
-/* out: pos e v w F T Fbb Tbb Fc Tc Fwca (11 x 3 doubles), then m, I */
+/* out: pos e v w F T Fbb Tbb Fc Tc Fwca Fc_next Tc_next (13 x 3 doubles),
+ * then m, I.  Fc, Tc entered the last integration; Fc_next, Tc_next come
+ * from the conversion that followed it and enter the next one. */
 int or_body_state(const or_sim *s, int id, double *out)
 {
     if (id < 0 || id >= s->nbody) return -1;
     const or_body *B = &s->body[id];
-    const double *src[11] = {B->pos, B->e, B->v, B->w, B->F, B->T, B->Fbb, B->Tbb, B->Fc, B->Tc, B->Fwca};
-    for (int a = 0; a < 11; ++a)
+    const double *src[13] = {B->pos, B->e, B->v, B->w, B->F, B->T, B->Fbb, B->Tbb,
+                             B->Fc, B->Tc, B->Fwca, B->Fcn, B->Tcn};
+    for (int a = 0; a < 13; ++a)
         for (int k = 0; k < 3; ++k) out[3 * a + k] = src[a][k];
-    out[33] = B->m;
-    out[34] = B->I;
+    out[39] = B->m;
+    out[40] = B->I;
     return 0;
 }
 

@@ -220,12 +220,12 @@ class OracleSim:
         lib().or_set_populations(self.h, fp)
 
     def body(self, i):
-        out = np.zeros(35)
+        out = np.zeros(41)
         if lib().or_body_state(self.h, int(i), out.ctypes.data_as(C.POINTER(C.c_double))):
             raise IndexError(i)
-        names = ["pos", "e", "v", "w", "F", "T", "Fbb", "Tbb", "Fc", "Tc", "Fwca"]
+        names = ["pos", "e", "v", "w", "F", "T", "Fbb", "Tbb", "Fc", "Tc", "Fwca", "Fc_next", "Tc_next"]
         d = {k: out[3 * a:3 * a + 3].copy() for a, k in enumerate(names)}
-        d["m"], d["I"] = out[33], out[34]
+        d["m"], d["I"] = out[39], out[40]
         return d
 
     def set_body(self, i, pos, e, v, w):
