@@ -104,7 +104,7 @@ typedef struct lb_params {
 /* One spherical squirmer, eq. (squirmer) with beta = B2/B1.
  *   pos   centre, lattice units, any real value (wrapped into the box);
  *   e     orientation (normalised by the library; LB_EINVAL if zero);
- *   R     radius (> 0.5); the box must satisfy 2*(ceil(R)+4)+1 <= min(n);
+ *   R     radius (> 0.5); the box must satisfy 2*(ceil(R)+3)+1 <= min(n);
  *   B1, beta  slip amplitude and dipolarity; B1 = 0 is a no-slip sphere;
  *   mode  LB_FREE (moves under F and T), LB_FIXED (never moves; F and T are
  *         still measured), LB_PRESCRIBED (moves with the given v, w);
@@ -134,13 +134,14 @@ int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n);
 /* Add a body (see lb_squirmer); *id receives its index (0, 1, ...).  The
  * cells inside it become solid at once (no conversion force at t = 0).
  * LB_EGEOM if it overlaps a wall or another body or is too large for the
- * box; LB_ESTATE after the first step. At most 253 bodies.               */
+ * box; LB_ESTATE after the first step. At most 252 bodies.               */
 int lb_add_squirmer(lb_sim *s, const lb_squirmer *sq, int *id);
 
-/* Enqueue nsteps time steps on the handle's stream.  Each step: geometry at
- * the current body positions, cell conversion, stream with bounce-back and
- * momentum exchange, TRT collision, force/torque reduction and rigid-body
- * update (WCA included).                                                   */
+/* Enqueue nsteps time steps on the handle's stream.  Each step: streaming
+ * with bounce-back and momentum exchange, TRT collision, rigid-body update
+ * from the force and torque (momentum exchange, WCA, and the conversion
+ * force of the previous move), then geometry at the new positions and cell
+ * conversion.  Between steps the cell owners match the body positions.     */
 int lb_step(lb_sim *s, int nsteps);
 
 /* Advance several independent handles by nsteps each.  Every handle runs

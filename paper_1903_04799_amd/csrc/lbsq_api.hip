@@ -17,16 +17,16 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     StepArgs args{};
     size_t esize = 4;
+    // double-buffered state; index cur holds the current time level
     void *f[2] = {nullptr, nullptr};
+    uint8_t *own[2] = {nullptr, nullptr};
+    DevBody *d_bodies[2] = {nullptr, nullptr};
     int cur = 0;
-    uint8_t *own = nullptr;
-    uint16_t *ev = nullptr;
-    DevBody *d_bodies = nullptr;
     std::vector<DevBody> bodies;
-    int *d_lists = nullptr;  // all_ids | all_start | mov_ids | mov_start
-    int nmov = 0, nblk_all = 0, nblk_mov = 0;
-    double *d_part = nullptr;
-    size_t part_blocks = 0;
+    int *d_lists = nullptr;  // mov_ids | mov_start | all_ids | all_start
+    int nmov = 0, nblk_mov = 0, nblk_all = 0;
+    unsigned long long *d_acc = nullptr;  // NACCSET sets of ACCSET_SIZE integer sums
+    size_t audit_blocks = 0;
     double *d_audit_part = nullptr, *d_audit_out = nullptr;
     int *d_err = nullptr;
     int64_t steps = 0;
@@ -67,7 +67,12 @@ void dev_free(lb_sim *s, void *p)
     else (void)hipFree(p);
 }
 
-int body_half_width(double R) { return int(std::ceil(R)) + 4; }
+// Half-width of a body's box around the floor of its position.  The cells
+// of a body lie within ceil(R) of that floor, its neighbour cells within
+// ceil(R) + 1, and in one step (|v| < 1) every owner or flag change stays
+// within ceil(R) + 2 of the old floor, inside the geometry box of half-width
+// H + 1.  One cell of margin on top.
+int body_half_width(double R) { return int(std::ceil(R)) + 2; }
 
 double wrap_pos(double p, int n)
 {
@@ -93,58 +98,65 @@ int sync_check(lb_sim *s)
     return LB_OK;
 }
 
+// Block ranges of the bodies' boxes (all bodies, and the moving ones).
 int rebuild_lists(lb_sim *s)
 {
     const int nb = int(s->bodies.size());
-    std::vector<int> all_ids(nb), all_start(nb + 1), mov_ids, mov_start(1, 0);
-    all_start[0] = 0;
+    std::vector<int> mov_ids, mov_start(1, 0), all_ids, all_start(1, 0);
     for (int b = 0; b < nb; ++b) {
-        all_ids[b] = b;
         const int side = 2 * s->bodies[b].H + 1;
-        const int blk = nblocks(uint64_t(side) * side * side);
-        all_start[b + 1] = all_start[b] + blk;
-        if (s->bodies[b].mode != LB_FIXED) {
-            mov_ids.push_back(b);
-            mov_start.push_back(mov_start.back() + blk);
-        }
+        all_ids.push_back(b);
+        all_start.push_back(all_start.back() + int((uint64_t(side) * side * side + CPB - 1) / CPB));
+        if (s->bodies[b].mode == LB_FIXED) continue;
+        // the geometry kernel walks the box grown by one cell on each side
+        const int gside = side + 2;
+        mov_ids.push_back(b);
+        mov_start.push_back(mov_start.back() + int((uint64_t(gside) * gside * gside + CPB - 1) / CPB));
     }
     s->nmov = int(mov_ids.size());
-    s->nblk_all = all_start[nb];
     s->nblk_mov = mov_start.back();
-    std::vector<int> packed;
+    s->nblk_all = all_start.back();
+    std::vector<int> packed(mov_ids);
+    packed.insert(packed.end(), mov_start.begin(), mov_start.end());
     packed.insert(packed.end(), all_ids.begin(), all_ids.end());
     packed.insert(packed.end(), all_start.begin(), all_start.end());
-    packed.insert(packed.end(), mov_ids.begin(), mov_ids.end());
-    packed.insert(packed.end(), mov_start.begin(), mov_start.end());
     if (hipMemcpy(s->d_lists, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return LB_EDEVICE;
-    if (size_t(s->nblk_all) > s->part_blocks) {
-        dev_free(s, s->d_part);
-        s->d_part = static_cast<double *>(dev_alloc(s, size_t(s->nblk_all) * 12 * sizeof(double)));
-        if (!s->d_part) return LB_ENOMEM;
-        s->part_blocks = size_t(s->nblk_all);
+    // audit partials: one per streaming block and one per boundary block
+    const size_t need = size_t(nblocks(s->args.box.n)) + size_t(s->nblk_all);
+    if (need > s->audit_blocks) {
+        dev_free(s, s->d_audit_part);
+        s->d_audit_part = static_cast<double *>(dev_alloc(s, need * 5 * sizeof(double)));
+        if (!s->d_audit_part) return LB_ENOMEM;
+        s->audit_blocks = need;
     }
     return LB_OK;
 }
 
+// the accumulator set that step number t writes its momentum exchange into
+unsigned long long *acc_set(lb_sim *s, int64_t t) { return s->d_acc + size_t(t % NACCSET) * ACCSET_SIZE; }
+
 void fill_launch(lb_sim *s, StepLaunch &L)
 {
-    const int nb = int(s->bodies.size());
+    const int c = s->cur, n = 1 - s->cur;
     L.args = s->args;
-    L.A = s->f[s->cur];
-    L.B = s->f[1 - s->cur];
-    L.own = s->own;
-    L.ev = s->ev;
-    L.bodies = s->d_bodies;
-    L.nbody = nb;
-    L.all_ids = s->d_lists;
-    L.all_start = s->d_lists + nb;
-    L.mov_ids = s->d_lists + 2 * nb + 1;
-    L.mov_start = s->d_lists + 2 * nb + 1 + s->nmov;
+    L.A = s->f[c];
+    L.B = s->f[n];
+    L.own_cur = s->own[c];
+    L.own_nxt = s->own[n];
+    L.bodies_cur = s->d_bodies[c];
+    L.bodies_nxt = s->d_bodies[n];
+    L.nbody = int(s->bodies.size());
+    L.mov_ids = s->d_lists;
+    L.mov_start = s->d_lists + s->nmov;
+    L.all_ids = s->d_lists + 2 * s->nmov + 1;
+    L.all_start = s->d_lists + 2 * s->nmov + 1 + L.nbody;
     L.nmov = s->nmov;
     L.nblk_mov = s->nblk_mov;
     L.nblk_all = s->nblk_all;
-    L.part = s->d_part;
+    L.acc_cur = acc_set(s, s->steps);
+    L.acc_conv = acc_set(s, s->steps + 1);
+    L.acc_clear = acc_set(s, s->steps + 2);
     L.audit_part = s->d_audit_part;
     L.audit_out = s->d_audit_out;
     L.err = s->d_err;
@@ -158,10 +170,27 @@ void fill_launch(lb_sim *s, StepLaunch &L)
 int pull_bodies(lb_sim *s)
 {
     if (s->bodies.empty()) return LB_OK;
-    if (hipMemcpy(s->bodies.data(), s->d_bodies, s->bodies.size() * sizeof(DevBody), hipMemcpyDeviceToHost) !=
+    if (hipMemcpy(s->bodies.data(), s->d_bodies[s->cur], s->bodies.size() * sizeof(DevBody),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return LB_EDEVICE;
+    return LB_OK;
+}
+
+// owners of the current buffer copied to the other one (set-up only)
+int mirror_owner(lb_sim *s)
+{
+    if (hipMemcpyAsync(s->own[1 - s->cur], s->own[s->cur], s->args.box.n, hipMemcpyDeviceToDevice, s->stream) !=
         hipSuccess)
         return LB_EDEVICE;
     return LB_OK;
+}
+
+int classify_now(lb_sim *s)
+{
+    if (!s->need_classify) return LB_OK;
+    if (launch_classify(s->args.box, s->own[s->cur], s->stream) != hipSuccess) return LB_EDEVICE;
+    s->need_classify = false;
+    return mirror_owner(s);
 }
 
 }  // namespace
@@ -192,13 +221,13 @@ int lb_destroy(lb_sim *s)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    dev_free(s, s->f[0]);
-    dev_free(s, s->f[1]);
-    dev_free(s, s->own);
-    dev_free(s, s->ev);
-    dev_free(s, s->d_bodies);
+    for (int k = 0; k < 2; ++k) {
+        dev_free(s, s->f[k]);
+        dev_free(s, s->own[k]);
+        dev_free(s, s->d_bodies[k]);
+    }
     dev_free(s, s->d_lists);
-    dev_free(s, s->d_part);
+    dev_free(s, s->d_acc);
     dev_free(s, s->d_audit_part);
     dev_free(s, s->d_audit_out);
     dev_free(s, s->d_err);
@@ -243,25 +272,27 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->esize = p->storage == LB_STORAGE_F32 ? 4 : 2;
 
     const size_t fbytes = size_t(Q) * bx.stride * s->esize;
-    s->f[0] = dev_alloc(s, fbytes);
-    s->f[1] = dev_alloc(s, fbytes);
-    s->own = static_cast<uint8_t *>(dev_alloc(s, n));
-    s->ev = static_cast<uint16_t *>(dev_alloc(s, n * sizeof(uint16_t)));
-    s->d_bodies = static_cast<DevBody *>(dev_alloc(s, MAXB * sizeof(DevBody)));
+    for (int k = 0; k < 2; ++k) {
+        s->f[k] = dev_alloc(s, fbytes);
+        s->own[k] = static_cast<uint8_t *>(dev_alloc(s, n));
+        s->d_bodies[k] = static_cast<DevBody *>(dev_alloc(s, MAXB * sizeof(DevBody)));
+    }
     s->d_lists = static_cast<int *>(dev_alloc(s, 4 * (MAXB + 1) * sizeof(int)));
+    s->d_acc = static_cast<unsigned long long *>(dev_alloc(s, NACCSET * ACCSET_SIZE * sizeof(unsigned long long)));
     s->d_audit_part = static_cast<double *>(dev_alloc(s, size_t(nblocks(n)) * 5 * sizeof(double)));
+    s->audit_blocks = size_t(nblocks(n));
     s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
     s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
-    if (!s->f[0] || !s->f[1] || !s->own || !s->ev || !s->d_bodies || !s->d_lists || !s->d_audit_part ||
-        !s->d_audit_out || !s->d_err) {
+    if (!s->f[0] || !s->f[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
+        !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err) {
         lb_destroy(s);
         return LB_ENOMEM;
     }
-    hipError_t e = hipSuccess;
-    e = hipMemsetAsync(s->f[0], 0, fbytes, s->stream);
+    hipError_t e = hipMemsetAsync(s->f[0], 0, fbytes, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_acc, 0, NACCSET * ACCSET_SIZE * sizeof(unsigned long long), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->f[1], 0, fbytes, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->own, 0, n, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->ev, 0, n * sizeof(uint16_t), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->own[0], 0, n, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->own[1], 0, n, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, NERR * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
@@ -280,7 +311,8 @@ int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n)
     std::vector<uint8_t> h(n);
     for (size_t c = 0; c < n; ++c) h[c] = solid[c] ? OWN_WALL : OWN_FLUID;
     (void)hipSetDevice(s->device);
-    if (hipMemcpy(s->own, h.data(), n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    for (int k = 0; k < 2; ++k)
+        if (hipMemcpy(s->own[k], h.data(), n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     s->need_classify = true;
     return LB_OK;
 }
@@ -305,7 +337,7 @@ int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
     std::memset(&B, 0, sizeof(B));
     B.H = body_half_width(q->R);
     const int side = 2 * B.H + 1;
-    if (side > std::min(bx.nx, std::min(bx.ny, bx.nz))) return LB_EGEOM;
+    if (side + 2 > std::min(bx.nx, std::min(bx.ny, bx.nz))) return LB_EGEOM;
     const int n3[3] = {bx.nx, bx.ny, bx.nz};
     for (int k = 0; k < 3; ++k) {
         B.pos[k] = wrap_pos(q->pos[k], n3[k]);
@@ -323,14 +355,16 @@ int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
     B.Rq = std::llrint(q->R * double(int64_t(1) << 20));
     const int b = int(s->bodies.size());
     (void)hipSetDevice(s->device);
-    if (hipMemcpy(s->d_bodies + b, &B, sizeof(B), hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
-    if (launch_body_cells(bx, s->d_bodies, b, side, s->own, 1, s->d_err, s->stream) != hipSuccess)
+    for (int k = 0; k < 2; ++k)
+        if (hipMemcpy(s->d_bodies[k] + b, &B, sizeof(B), hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    if (launch_body_cells(bx, s->d_bodies[s->cur], b, side, s->own[s->cur], 1, s->d_err, s->stream) != hipSuccess)
         return LB_EDEVICE;
     const int st = sync_check(s);
     if (st == LB_EGEOM) return LB_EGEOM;
     if (st != LB_OK) return st;
-    if (launch_body_cells(bx, s->d_bodies, b, side, s->own, 0, s->d_err, s->stream) != hipSuccess)
-        return LB_EDEVICE;
+    for (int k = 0; k < 2; ++k)
+        if (launch_body_cells(bx, s->d_bodies[s->cur], b, side, s->own[k], 0, s->d_err, s->stream) != hipSuccess)
+            return LB_EDEVICE;
     s->bodies.push_back(B);
     const int rc = rebuild_lists(s);
     if (rc != LB_OK) return rc;
@@ -343,10 +377,8 @@ int lb_step(lb_sim *s, int nsteps)
 {
     if (!s || nsteps < 0) return LB_EINVAL;
     (void)hipSetDevice(s->device);
-    if (s->need_classify) {
-        if (launch_classify(s->args.box, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
-        s->need_classify = false;
-    }
+    const int cl = classify_now(s);
+    if (cl != LB_OK) return cl;
     s->started = true;
     for (int t = 0; t < nsteps; ++t) {
         StepLaunch L;
@@ -395,7 +427,7 @@ int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
     uint8_t *d_o = static_cast<uint8_t *>(dev_alloc(s, n));
     int rc = LB_OK;
     if (!d_rho || !d_u || !d_o) rc = LB_ENOMEM;
-    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f[s->cur], s->own, d_rho, d_u, d_o, s->stream) !=
+    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], d_rho, d_u, d_o, s->stream) !=
                            hipSuccess)
         rc = LB_EDEVICE;
     if (rc == LB_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LB_EDEVICE;
@@ -465,19 +497,17 @@ int lb_links(lb_sim *s, uint32_t *cell, uint8_t *dir, uint8_t *owner, size_t cap
     if (st != LB_OK) return st;
     const Box &bx = s->args.box;
     (void)hipSetDevice(s->device);
-    if (s->need_classify) {
-        if (launch_classify(bx, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
-        s->need_classify = false;
-    }
+    st = classify_now(s);
+    if (st != LB_OK) return st;
     uint32_t *d_mask = static_cast<uint32_t *>(dev_alloc(s, size_t(bx.n) * sizeof(uint32_t)));
     if (!d_mask) return LB_ENOMEM;
     std::vector<uint32_t> mask(bx.n);
     std::vector<uint8_t> own(bx.n);
     int rc = LB_OK;
-    if (launch_link_mask(bx, s->own, d_mask, s->stream) != hipSuccess ||
+    if (launch_link_mask(bx, s->own[s->cur], d_mask, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess ||
         hipMemcpy(mask.data(), d_mask, size_t(bx.n) * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(own.data(), s->own, bx.n, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(own.data(), s->own[s->cur], bx.n, hipMemcpyDeviceToHost) != hipSuccess)
         rc = LB_EDEVICE;
     dev_free(s, d_mask);
     if (rc != LB_OK) return rc;
@@ -514,7 +544,7 @@ int lb_read_populations(lb_sim *s, double *f)
     if (!buf) return LB_ENOMEM;
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
-        if (launch_plane(s->p.storage, s->args, s->f[s->cur], s->own, i, buf, 1, s->stream) != hipSuccess ||
+        if (launch_plane(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], i, buf, 1, s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess ||
             hipMemcpy(f + size_t(i) * n, buf, size_t(n) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             rc = LB_EDEVICE;
@@ -534,7 +564,7 @@ int lb_write_populations(lb_sim *s, const double *f)
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
         if (hipMemcpy(buf, f + size_t(i) * n, size_t(n) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            launch_plane(s->p.storage, s->args, s->f[s->cur], s->own, i, buf, 0, s->stream) != hipSuccess ||
+            launch_plane(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], i, buf, 0, s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess)
             rc = LB_EDEVICE;
     }
@@ -546,7 +576,7 @@ static int audit_now(lb_sim *s, double out[5])
 {
     int st = sync_check(s);
     if (st != LB_OK) return st;
-    if (launch_audit(s->p.storage, s->args, s->f[s->cur], s->own, s->d_audit_part, s->d_audit_out, s->d_err,
+    if (launch_audit(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], s->d_audit_part, s->d_audit_out, s->d_err,
                      s->stream) != hipSuccess)
         return LB_EDEVICE;
     st = sync_check(s);
@@ -580,7 +610,9 @@ int lb_info(lb_sim *s, uint64_t *n_fluid, int64_t *steps)
 }
 
 // ---------------------------------------------------------------------------
-// checkpoint blob: header, populations (storage format), owners, bodies
+// checkpoint blob: header, populations (storage format), owners, bodies and
+// both force-accumulator sets (they hold the conversion force still to be
+// applied by the next integration)
 
 struct StateHeader {
     uint64_t magic;
@@ -589,13 +621,14 @@ struct StateHeader {
     uint64_t pop_bytes;
 };
 
-static constexpr uint64_t STATE_MAGIC = 0x31717362'6c62ull;
+static constexpr uint64_t STATE_MAGIC = 0x34717362'6c62ull;
+static constexpr size_t ACC_BYTES = NACCSET * ACCSET_SIZE * sizeof(unsigned long long);
 
 int lb_state_size(lb_sim *s, size_t *bytes)
 {
     if (!s || !bytes) return LB_EINVAL;
     *bytes = sizeof(StateHeader) + size_t(Q) * s->args.box.stride * s->esize + s->args.box.n +
-             MAXB * sizeof(DevBody);
+             s->bodies.size() * sizeof(DevBody) + ACC_BYTES;
     return LB_OK;
 }
 
@@ -607,49 +640,53 @@ int lb_save_state(lb_sim *s, void *buf, size_t bytes)
     if (st != LB_OK) return st;
     st = pull_bodies(s);
     if (st != LB_OK) return st;
-    if (s->need_classify) {
-        if (launch_classify(s->args.box, s->own, s->stream) != hipSuccess) return LB_EDEVICE;
-        s->need_classify = false;
-        if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
-    }
+    st = classify_now(s);
+    if (st != LB_OK) return st;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
     StateHeader h{STATE_MAGIC, s->p.nx, s->p.ny, s->p.nz, s->p.storage, s->p.scale_log2,
                   int32_t(s->bodies.size()), s->steps, uint64_t(Q) * s->args.box.stride * s->esize};
     char *p = static_cast<char *>(buf);
-    std::memset(p, 0, need);
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
     if (hipMemcpy(p, s->f[s->cur], h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
-    if (hipMemcpy(p, s->own, s->args.box.n, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    if (hipMemcpy(p, s->own[s->cur], s->args.box.n, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += s->args.box.n;
     if (!s->bodies.empty()) std::memcpy(p, s->bodies.data(), s->bodies.size() * sizeof(DevBody));
+    p += s->bodies.size() * sizeof(DevBody);
+    if (hipMemcpy(p, s->d_acc, ACC_BYTES, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     return LB_OK;
 }
 
 int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
 {
-    size_t need = 0;
-    if (!buf || lb_state_size(s, &need) != LB_OK || bytes < need) return LB_EINVAL;
+    if (!s || !buf || bytes < sizeof(StateHeader)) return LB_EINVAL;
     StateHeader h;
     std::memcpy(&h, buf, sizeof(h));
     if (h.magic != STATE_MAGIC || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
         h.storage != s->p.storage || h.scale_log2 != s->p.scale_log2 || h.nbody < 0 || h.nbody > MAXB ||
         h.pop_bytes != uint64_t(Q) * s->args.box.stride * s->esize)
         return LB_EINVAL;
+    const size_t need = sizeof(h) + h.pop_bytes + s->args.box.n + size_t(h.nbody) * sizeof(DevBody) + ACC_BYTES;
+    if (bytes < need) return LB_EINVAL;
     int st = sync_check(s);
     if (st != LB_OK) return st;
     const char *p = static_cast<const char *>(buf) + sizeof(h);
     if (hipMemcpy(s->f[s->cur], p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
-    if (hipMemcpy(s->own, p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    for (int k = 0; k < 2; ++k)
+        if (hipMemcpy(s->own[k], p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     p += s->args.box.n;
     s->bodies.assign(h.nbody, DevBody{});
     if (h.nbody) {
         std::memcpy(s->bodies.data(), p, size_t(h.nbody) * sizeof(DevBody));
-        if (hipMemcpy(s->d_bodies, s->bodies.data(), size_t(h.nbody) * sizeof(DevBody), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return LB_EDEVICE;
+        for (int k = 0; k < 2; ++k)
+            if (hipMemcpy(s->d_bodies[k], s->bodies.data(), size_t(h.nbody) * sizeof(DevBody),
+                          hipMemcpyHostToDevice) != hipSuccess)
+                return LB_EDEVICE;
     }
+    p += size_t(h.nbody) * sizeof(DevBody);
+    if (hipMemcpy(s->d_acc, p, ACC_BYTES, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     st = rebuild_lists(s);
     if (st != LB_OK) return st;
     s->steps = h.steps;

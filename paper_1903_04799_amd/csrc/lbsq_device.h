@@ -13,15 +13,21 @@ namespace lbsq {
 
 constexpr int Q = 19;
 constexpr int BLOCK = 256;
-constexpr int MAXB = 253;
+constexpr int MAXB = 252;
+// cells per block of the kernels that work on the bodies' boxes with one
+// thread per (cell, direction): 13 x 19 = 247 of 256 threads
+constexpr int CPB = 13;
 
-// Cell owner codes.  Fluid cells carry a flag telling the fused kernel
-// whether any of their 18 neighbours is solid (the slow path).
+// Cell owner codes.  Fluid cells carry a flag saying which of their 18
+// neighbours are solid: none (the streaming kernel's fast path), static
+// walls only (the streaming kernel reflects them), or at least one body
+// cell (the boundary kernel takes the cell).
 constexpr uint8_t OWN_FLUID = 0;
-constexpr uint8_t OWN_FLUID_NB = 254;
+constexpr uint8_t OWN_NB_WALL = 253;
+constexpr uint8_t OWN_NB_BODY = 254;
 constexpr uint8_t OWN_WALL = 255;
 
-__host__ __device__ constexpr bool is_fluid(uint8_t o) { return o == OWN_FLUID || o == OWN_FLUID_NB; }
+__host__ __device__ constexpr bool is_fluid(uint8_t o) { return o == OWN_FLUID || o == OWN_NB_WALL || o == OWN_NB_BODY; }
 __host__ __device__ constexpr bool is_body(uint8_t o) { return o >= 1 && o <= MAXB; }
 
 // D3Q19 in the canonical order of the C ABI (rest, faces, edges; for odd i
@@ -44,6 +50,19 @@ __host__ __device__ constexpr int cz(int i)
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr float wgtf(int i) { return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f); }
+
+// The same lattice for a direction index known only at run time: bit masks
+// of the directions whose component is +1 and -1 (compact code for loops
+// that are not unrolled).
+__host__ __device__ constexpr int rcx(int i) { return int((0x2a82u >> i) & 1u) - int((0x5504u >> i) & 1u); }
+__host__ __device__ constexpr int rcy(int i) { return int((0x28488u >> i) & 1u) - int((0x50310u >> i) & 1u); }
+__host__ __device__ constexpr int rcz(int i) { return int((0x4c820u >> i) & 1u) - int((0x33040u >> i) & 1u); }
+
+__host__ __device__ constexpr bool lattice_tables_agree(int i)
+{
+    return i == Q || (rcx(i) == cx(i) && rcy(i) == cy(i) && rcz(i) == cz(i) && lattice_tables_agree(i + 1));
+}
+static_assert(lattice_tables_agree(0), "run-time D3Q19 masks disagree with the lattice");
 
 // ---------------------------------------------------------------------------
 // Population storage: deviations d_i = f_i - w_i rho0, times 2^k.
@@ -89,6 +108,61 @@ struct DevBody {
     int64_t Rq;  // radius in 2^-20 quanta
 };
 
+// What the geometry kernel needs of a body at its new position (kept in
+// LDS): floor of the position, the position's offset from it in 2^-20
+// quanta (rounded half to even), the squared radius in quanta, and the
+// rigid-body velocity for refills.
+struct GeoBody {
+    double pos[3], v[3], w[3];
+    int ip[3], pq[3];
+    int64_t Rq2;
+    int H;
+};
+
+// What the boundary kernel needs of a body for its links (kept in LDS),
+// relative to the floor of the position.
+struct LinkBody {
+    int ip[3];
+    int H;
+    float fr[3], v[3], w[3], e[3];
+    float B1, beta;
+};
+
+// Forces and torques are accumulated in integers, so that the sums are
+// bit-identical in any order.  Per body:
+//   [0..2]   momentum exchange without the pressure part, 2^-44 fixed point
+//   [3..5]   its torque, 2^-44 fixed point
+//   [6..8]   conversion force, 2^-44 fixed point
+//   [9..11]  conversion torque, 2^-44 fixed point
+//   [12..14] Kf = sum over links of k_i c_i (k = 2 on faces, 1 on edges)
+//   [15..17] Kr = sum over links of k_i (2 r + 1) x c_i, r the source cell
+//            relative to the floor of the body position
+// The pressure part of the momentum exchange, -c_i 2 w_i rho0 per link, is
+// -(rho0/18) Kf in total, and its torque -(rho0/18)(Kr/2 - p x Kf) with p
+// the position minus its floor: both exact up to one final rounding, so the
+// pressure terms of a closed surface cancel exactly.  Three sets rotate over
+// the steps (written, read, cleared).
+constexpr int NACC = 18;
+constexpr int NACCSET = 3;
+// each set keeps NCOPY copies, picked by block index, so that the atomics of
+// many blocks do not pile up on the same addresses; the body update sums them
+constexpr int NCOPY = 16;
+constexpr int ACCSET_SIZE = NCOPY * MAXB * NACC;  // integers per set
+// up to this many bodies every geometry block repeats the body update instead
+// of waiting for a separate one-block launch
+constexpr int FUSE_MAX = 8;
+constexpr double FX_SCALE = 17592186044416.0;  // 2^44
+__device__ __forceinline__ long long to_fx(double v) { return __double2ll_rn(v * FX_SCALE); }
+__device__ __forceinline__ double from_fx(unsigned long long v) { return double(static_cast<long long>(v)) / FX_SCALE; }
+
+// Wrap an integer difference in (-2n, 2n) into [0, n).
+__device__ __forceinline__ int wrap_small(int a, int n)
+{
+    if (a < 0) a += n;
+    if (a >= n) a -= n;
+    return a;
+}
+
 struct Box {
     int nx, ny, nz;
     uint32_t n;       // cells
@@ -110,7 +184,8 @@ __device__ __forceinline__ int wrap(int a, int n)
 }
 
 // Lever arm from the body centre to the centre of cell (x, y, z).
-__device__ __forceinline__ void lever_arm(const Box &b, const DevBody &B, int x, int y, int z, double d[3])
+template <class BT>
+__device__ __forceinline__ void lever_arm(const Box &b, const BT &B, int x, int y, int z, double d[3])
 {
     d[0] = min_image((x + 0.5) - B.pos[0], b.nx);
     d[1] = min_image((y + 0.5) - B.pos[1], b.ny);
@@ -118,8 +193,11 @@ __device__ __forceinline__ void lever_arm(const Box &b, const DevBody &B, int x,
 }
 
 // Inside test in int64 fixed point (2^-20 quanta, centres at i + 1/2, ties
-// inside, positions rounded half to even).
-__device__ __forceinline__ bool inside_body(const Box &b, const DevBody &B, int x, int y, int z)
+// inside, positions rounded half to even).  Body positions are kept in
+// [0, n), so X - P lies in (-L, L) and one conditional wrap gives the
+// minimum image.
+template <class BT>
+__device__ __forceinline__ bool inside_body(const Box &b, const BT &B, int x, int y, int z)
 {
     const int64_t ONE = int64_t(1) << 20;
     const int n[3] = {b.nx, b.ny, b.nz};
@@ -130,26 +208,29 @@ __device__ __forceinline__ bool inside_body(const Box &b, const DevBody &B, int 
         const int64_t X = (2 * int64_t(c[k]) + 1) * (ONE / 2);
         const int64_t P = __double2ll_rn(B.pos[k] * double(ONE));
         const int64_t L = int64_t(n[k]) * ONE;
-        int64_t D = (X - P) % L;
-        if (D < 0) D += L;
+        int64_t D = X - P;
         if (D >= L / 2) D -= L;
+        else if (D < -(L / 2)) D += L;
         sum += D * D;
     }
     return sum <= B.Rq * B.Rq;
 }
 
-// Bounding box of a body: cells floor(pos) - H ... floor(pos) + H per axis.
-__device__ __forceinline__ void bbox_origin(const DevBody &B, int o[3])
+// Bounding box of a body: cells floor(pos) - H - g ... floor(pos) + H + g per
+// axis (g = 0, or 1 for the box that also covers the next position).
+template <class BT>
+__device__ __forceinline__ void bbox_origin(const BT &B, int o[3], int g = 0)
 {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) o[k] = static_cast<int>(floor(B.pos[k])) - B.H;
+    for (int k = 0; k < 3; ++k) o[k] = static_cast<int>(floor(B.pos[k])) - B.H - g;
 }
 
-__device__ __forceinline__ bool in_bbox(const Box &b, const DevBody &B, int x, int y, int z)
+template <class BT>
+__device__ __forceinline__ bool in_bbox(const Box &b, const BT &B, int x, int y, int z, int g = 0)
 {
     int o[3];
-    bbox_origin(B, o);
-    const int side = 2 * B.H + 1;
+    bbox_origin(B, o, g);
+    const int side = 2 * (B.H + g) + 1;
     return wrap(x - o[0], b.nx) < side && wrap(y - o[1], b.ny) < side && wrap(z - o[2], b.nz) < side;
 }
 
@@ -161,8 +242,8 @@ __device__ __forceinline__ void wall_velocity(const DevBody &B, const double d[3
     vb[1] = B.v[1] + B.w[2] * d[0] - B.w[0] * d[2];
     vb[2] = B.v[2] + B.w[0] * d[1] - B.w[1] * d[0];
     if (B.B1 != 0.0) {
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double n[3] = {d[0] / r, d[1] / r, d[2] / r};
+        const double ir = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double n[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
         const double en = B.e[0] * n[0] + B.e[1] * n[1] + B.e[2] * n[2];
         const double a = B.B1 * (1.0 + B.beta * en);
 #pragma unroll
@@ -176,7 +257,7 @@ __device__ __forceinline__ float bounce_shift(int i, float rho_w, const DevBody 
 {
     double vb[3];
     wall_velocity(B, d, vb);
-    const double cv = cx(i) * vb[0] + cy(i) * vb[1] + cz(i) * vb[2];
+    const double cv = rcx(i) * vb[0] + rcy(i) * vb[1] + rcz(i) * vb[2];
     return static_cast<float>(6.0 * wgt(i) * static_cast<double>(rho_w) * cv);
 }
 

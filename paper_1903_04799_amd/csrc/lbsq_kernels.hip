@@ -1,32 +1,38 @@
 // lbsq_kernels.hip -- gfx950 kernels of the lattice Boltzmann squirmer library
 // (arXiv:1903.04799).
 //
-// One time step is five launches on the handle's stream:
-//   k_geom      integer inside test over each moving body's bounding box:
-//               new owners and covered/uncovered events (fixed point, exact);
-//   k_refill    neighbour-solid flags and the refill of uncovered cells with
-//               the equilibrium at the mean neighbour density and the rigid
-//               body velocity (cell conversion, Sec. "Numerical Method");
-//   k_force     momentum exchange eqs. (bbforce), (bbtorque) over the links
-//               of every body plus the conversion force eq. (consforce), as
-//               FP64 per-block partials;
-//   k_stream_collide  the hot loop: pull streaming with moving-wall
-//               bounce-back and the TRT collision of eq. (lb), FP32 math on
-//               stored deviations;
-//   k_body      fixed-order FP64 reduction of the partials, WCA eq. (wca),
-//               symplectic Euler.
+// A time step t is three launches on one stream:
+//   k_stream_collide  pull streaming and the TRT collision of eq. (lb) for
+//                     every fluid cell that has no body neighbour (static
+//                     walls are reflected in place): FP32 arithmetic on stored
+//                     deviations, A(t) -> B, non-temporal stores;
+//   k_boundary        the cells next to a body, found in the bodies' boxes:
+//                     the same update with moving-wall bounce-back carrying
+//                     the rigid-body velocity eq. (vb) plus the squirmer slip
+//                     eq. (squirmer), and the momentum exchange of their
+//                     links, eqs. (bbforce), (bbtorque), accumulated as
+//                     fixed-point integers;
+//   k_geoconv         the body update (decode of the integer force sums, WCA
+//                     eq. (wca), symplectic Euler), repeated by every block
+//                     when there are few bodies, else done before by the
+//                     one-block k_body; then, over each moving
+//                     body's box, the integer inside test at the new
+//                     positions gives new owners and neighbour flags, and the
+//                     cell conversion of Sec. "Numerical Method" refills
+//                     uncovered cells and accumulates the conversion force
+//                     eq. (consforce) for the next integration.
+// Owners and the body table are double-buffered (time t is read while time
+// t+1 is written); force sums rotate over three accumulator sets.
 #include "lbsq_device.h"
 #include "lbsq_launch.h"
 
 namespace lbsq {
 
-constexpr uint16_t EV_COVERED = 0x100;
-constexpr uint16_t EV_UNCOVERED = 0x200;
-
 // ---------------------------------------------------------------------------
-// block reductions in FP64 (fixed order: xor-shuffle tree inside a wave, then
-// wave 0 sums the per-wave results in wave order)
+// reductions
 
+// FP64 block reduction in a fixed order (xor-shuffle tree inside each wave,
+// then the wave results in wave order); result in out[0..K) from threads < K.
 template <int K>
 __device__ __forceinline__ void block_reduce(double (&v)[K], double *out)
 {
@@ -51,35 +57,57 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double *out)
     }
 }
 
-// ---------------------------------------------------------------------------
-// bounding-box work distribution: blocks [start[m], start[m+1]) cover the
-// (2H+1)^3 cells of the m-th listed body
-
-struct BoxCell {
-    int m;  // position in the body list
-    int x, y, z;
-    bool valid;
-};
-
-__device__ __forceinline__ BoxCell box_cell(const Box &bx, const DevBody *bodies, const int *ids,
-                                            const int *start, int nlist)
+// Integer block reduction of N values; result in out[0..N) from threads < N
+// (integer sums: any order gives the same result).
+template <int N>
+__device__ __forceinline__ void block_reduce_i64(long long (&v)[N], long long *out)
 {
-    BoxCell r;
-    const int blk = blockIdx.x;
-    int m = 0;
-    while (m + 1 < nlist && blk >= start[m + 1]) ++m;
-    r.m = m;
-    const DevBody &B = bodies[ids[m]];
-    const int side = 2 * B.H + 1;
-    const uint32_t l = uint32_t(blk - start[m]) * BLOCK + threadIdx.x;
-    r.valid = l < uint32_t(side) * side * side;
-    int o[3];
-    bbox_origin(B, o);
-    const int lx = l % side, ly = (l / side) % side, lz = l / (side * side);
-    r.x = wrap(o[0] + lx, bx.nx);
-    r.y = wrap(o[1] + ly, bx.ny);
-    r.z = wrap(o[2] + lz, bx.nz);
-    return r;
+    __shared__ long long red[BLOCK / 64][N];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        long long x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[k] = x;
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[wid][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        long long s = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Add the integer vectors v of all lanes with the same key (a body index;
+// key < 0 = nothing) into acc[key * NACC + slot[k]].  Called by whole waves;
+// one atomic per component and distinct key in the wave.
+template <int N>
+__device__ __forceinline__ void wave_accumulate(int key, const long long (&v)[N], const int (&slot)[N],
+                                                unsigned long long *acc)
+{
+    unsigned long long pending = __ballot(key >= 0);
+    const int lane = threadIdx.x & 63;
+    while (pending) {
+        const int leader = __ffsll(static_cast<long long>(pending)) - 1;
+        const int kb = __shfl(key, leader, 64);
+        const bool mine = key == kb;
+        long long s[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            s[k] = mine ? v[k] : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, 64);
+        }
+        if (lane == leader)
+#pragma unroll
+            for (int k = 0; k < N; ++k) atomicAdd(&acc[kb * NACC + slot[k]], static_cast<unsigned long long>(s[k]));
+        pending &= ~__ballot(mine);
+    }
 }
 
 __device__ __forceinline__ uint32_t cell_of(const Box &bx, int x, int y, int z)
@@ -87,336 +115,143 @@ __device__ __forceinline__ uint32_t cell_of(const Box &bx, int x, int y, int z)
     return uint32_t(x) + uint32_t(bx.nx) * (uint32_t(y) + uint32_t(bx.ny) * uint32_t(z));
 }
 
-// the lowest-listed moving body whose box contains the cell does the
-// per-cell (not per-body) work, so every cell is written by one thread only
-__device__ __forceinline__ bool first_box(const Box &bx, const DevBody *bodies, const int *ids, int m,
-                                          int x, int y, int z)
-{
-    for (int mm = 0; mm < m; ++mm)
-        if (in_bbox(bx, bodies[ids[mm]], x, y, z)) return false;
-    return true;
-}
-
 // ---------------------------------------------------------------------------
-// geometry
+// the collision, shared by the streaming and boundary kernels
 
-__global__ __launch_bounds__(BLOCK) void k_geom(Box bx, const DevBody *__restrict__ bodies, int nbody,
-                                                const int *__restrict__ ids, const int *__restrict__ start,
-                                                int nlist, uint8_t *__restrict__ own,
-                                                uint16_t *__restrict__ ev, int *__restrict__ err)
-{
-    const BoxCell bc = box_cell(bx, bodies, ids, start, nlist);
-    if (!bc.valid || !first_box(bx, bodies, ids, bc.m, bc.x, bc.y, bc.z)) return;
-    const uint32_t c = cell_of(bx, bc.x, bc.y, bc.z);
-    const uint8_t old = own[c];
-    if (old == OWN_WALL) {
-        ev[c] = 0;
-        return;
+// Neighbour offsets (mod 2^32) of cell idx in a periodic box.
+struct Nbr {
+    uint32_t idx, x, y, z;
+    uint32_t oxm, oxp, oym, oyp, ozm, ozp;
+    __device__ __forceinline__ Nbr(const Box &bx, uint32_t i) : idx(i)
+    {
+        const uint32_t nx = bx.nx, ny = bx.ny, nz = bx.nz, pl = nx * ny;
+        x = i % nx;
+        const uint32_t yz = i / nx;
+        y = yz % ny;
+        z = yz / ny;
+        oxm = x == 0 ? nx - 1 : uint32_t(-1);
+        oxp = x == nx - 1 ? uint32_t(1) - nx : 1u;
+        oym = y == 0 ? (ny - 1) * nx : uint32_t(0) - nx;
+        oyp = y == ny - 1 ? uint32_t(0) - (ny - 1) * nx : nx;
+        ozm = z == 0 ? (nz - 1) * pl : uint32_t(0) - pl;
+        ozp = z == nz - 1 ? uint32_t(0) - (nz - 1) * pl : pl;
     }
-    uint8_t nw = OWN_FLUID;
-    bool clash = false;
-    for (int b = 0; b < nbody; ++b) {
-        if (!in_bbox(bx, bodies[b], bc.x, bc.y, bc.z)) continue;
-        if (inside_body(bx, bodies[b], bc.x, bc.y, bc.z)) {
-            if (nw != OWN_FLUID) clash = true;
-            else nw = uint8_t(b + 1);
-        }
+    // source cell x - c_i of the pull
+    __device__ __forceinline__ uint32_t src(int i) const
+    {
+        uint32_t s = idx;
+        if (cx(i) == 1) s += oxm;
+        else if (cx(i) == -1) s += oxp;
+        if (cy(i) == 1) s += oym;
+        else if (cy(i) == -1) s += oyp;
+        if (cz(i) == 1) s += ozm;
+        else if (cz(i) == -1) s += ozp;
+        return s;
     }
-    if (clash) err[0] = 1;
-    uint16_t e = 0;
-    if (nw != OWN_FLUID) {
-        if (is_fluid(old)) e = EV_COVERED | nw;
-        if (old != nw) own[c] = nw;
-    } else if (is_body(old)) {
-        e = EV_UNCOVERED | old;
-        own[c] = OWN_FLUID;
-    }
-    ev[c] = e;
-}
+};
 
-// density of cell c from stored deviations, FP64
-template <class S>
-__device__ __forceinline__ double cell_density(const typename S::T *A, uint64_t stride, uint32_t c,
-                                               double rho0, float inv)
+// TRT collision of the incoming deviations f, stored to B[.][idx]; the audit
+// adds what was stored (as it will be read back).
+template <class S, bool AUDIT, bool FORCE>
+__device__ __forceinline__ void collide_store(const StepArgs &a, const float (&f)[Q], typename S::T *__restrict__ Bf,
+                                              uint32_t idx, double (&am)[5])
 {
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) r += double(S::ld(A[i * stride + c], inv));
-    return rho0 + r;
-}
-
-// mean density of the D3Q19 neighbours that are fluid at both time levels
-template <class S>
-__device__ __forceinline__ double refill_density(const Box &bx, const typename S::T *A, const uint8_t *own,
-                                                 const uint16_t *ev, int x, int y, int z, double rho0,
-                                                 float inv)
-{
-    double sum = 0.0;
-    int cnt = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const uint32_t n = cell_of(bx, wrap(x + cx(i), bx.nx), wrap(y + cy(i), bx.ny), wrap(z + cz(i), bx.nz));
-        if (is_fluid(own[n]) && !(ev[n] & EV_UNCOVERED)) {
-            sum += cell_density<S>(A, bx.stride, n, rho0, inv);
-            ++cnt;
-        }
-    }
-    return cnt ? sum / cnt : rho0;
-}
-
-template <class S>
-__global__ __launch_bounds__(BLOCK) void k_refill(StepArgs a, const DevBody *__restrict__ bodies,
-                                                  const int *__restrict__ ids, const int *__restrict__ start,
-                                                  int nlist, uint8_t *__restrict__ own,
-                                                  const uint16_t *__restrict__ ev, typename S::T *__restrict__ A)
-{
-    const Box &bx = a.box;
-    const BoxCell bc = box_cell(bx, bodies, ids, start, nlist);
-    if (!bc.valid || !first_box(bx, bodies, ids, bc.m, bc.x, bc.y, bc.z)) return;
-    const uint32_t c = cell_of(bx, bc.x, bc.y, bc.z);
-    const uint8_t o = own[c];
-    if (!is_fluid(o)) return;
-    bool nb = false;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const uint32_t n = cell_of(bx, wrap(bc.x + cx(i), bx.nx), wrap(bc.y + cy(i), bx.ny), wrap(bc.z + cz(i), bx.nz));
-        nb |= !is_fluid(own[n]);
-    }
-    const uint8_t flag = nb ? OWN_FLUID_NB : OWN_FLUID;
-    if (flag != o) own[c] = flag;
-    const uint16_t e = ev[c];
-    if (!(e & EV_UNCOVERED)) return;
-    const DevBody &B = bodies[(e & 0xff) - 1];
-    const double rb = refill_density<S>(bx, A, own, ev, bc.x, bc.y, bc.z, a.rho0d, a.inv_scale);
-    double d[3], u[3];
-    lever_arm(bx, B, bc.x, bc.y, bc.z, d);
-    u[0] = B.v[0] + B.w[1] * d[2] - B.w[2] * d[1];
-    u[1] = B.v[1] + B.w[2] * d[0] - B.w[0] * d[2];
-    u[2] = B.v[2] + B.w[0] * d[1] - B.w[1] * d[0];
-    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-        const double dev = wgt(i) * (rb - a.rho0d) + wgt(i) * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        A[i * bx.stride + c] = S::st(float(dev), a.scale);
+        drho += f[i];
+        if (cx(i)) jx += cx(i) * f[i];
+        if (cy(i)) jy += cy(i) * f[i];
+        if (cz(i)) jz += cz(i) * f[i];
+    }
+    if (FORCE) {
+        jx += 0.5f * a.g[0];
+        jy += 0.5f * a.g[1];
+        jz += 0.5f * a.g[2];
+    }
+    const float rho = a.rho0 + drho;
+    const float ir = 1.0f / rho;
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float le = a.lam_e, lo = a.lam_o;
+    float out[Q];
+    out[0] = f[0] - le * (f[0] - wgtf(0) * (drho - 1.5f * rho * usq));
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const int ib = i + 1;
+        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        const float ep = wgtf(i) * (drho + rho * (4.5f * cu * cu - 1.5f * usq));
+        const float em = wgtf(i) * rho * 3.0f * cu;
+        const float fp = 0.5f * (f[i] + f[ib]), fm = 0.5f * (f[i] - f[ib]);
+        const float de = le * (fp - ep), dodd = lo * (fm - em);
+        out[i] = f[i] - de - dodd;
+        out[ib] = f[ib] - de + dodd;
+    }
+    if (FORCE) {
+        const float ug = ux * a.g[0] + uy * a.g[1] + uz * a.g[2];
+        const float ce = 1.0f - 0.5f * le, co = 1.0f - 0.5f * lo;
+        out[0] += ce * wgtf(0) * (-3.0f * ug);
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+            const float cg = cx(i) * a.g[0] + cy(i) * a.g[1] + cz(i) * a.g[2];
+            const float se = wgtf(i) * (9.0f * cu * cg - 3.0f * ug);
+            const float so = 3.0f * wgtf(i) * cg;
+            out[i] += ce * se + co * so;
+            out[i + 1] += ce * se - co * so;
+        }
+    }
+    const uint64_t st = a.box.stride;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(S::st(out[i], a.scale), &Bf[i * st + idx]);
+    if (AUDIT) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double v = S::ld(S::st(out[i], a.scale), a.inv_scale);
+            am[0] += v;
+            am[1] += cx(i) * v;
+            am[2] += cy(i) * v;
+            am[3] += cz(i) * v;
+        }
+        am[4] = 1.0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// momentum exchange and conversion force, per-block FP64 partials
-// partial layout: Fbb[3] Tbb[3] Fc[3] Tc[3]
-
-template <class S>
-__global__ __launch_bounds__(BLOCK) void k_force(StepArgs a, const DevBody *__restrict__ bodies,
-                                                 const int *__restrict__ ids, const int *__restrict__ start,
-                                                 int nlist, const uint8_t *__restrict__ own,
-                                                 const uint16_t *__restrict__ ev,
-                                                 const typename S::T *__restrict__ A, double *__restrict__ part)
-{
-    const Box &bx = a.box;
-    const BoxCell bc = box_cell(bx, bodies, ids, start, nlist);
-    const int b = ids[bc.m];
-    const DevBody &B = bodies[b];
-    double acc[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-    if (bc.valid) {
-        const uint32_t c = cell_of(bx, bc.x, bc.y, bc.z);
-        const uint8_t o = own[c];
-        const uint8_t me = uint8_t(b + 1);
-        if (o == OWN_FLUID_NB) {
-            float fo[Q];
-            float rw = 0.0f;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                fo[i] = S::ld(A[i * bx.stride + c], a.inv_scale);
-                rw += fo[i];
-            }
-            rw += a.rho0;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int sx = wrap(bc.x - cx(i), bx.nx), sy = wrap(bc.y - cy(i), bx.ny), sz = wrap(bc.z - cz(i), bx.nz);
-                if (own[cell_of(bx, sx, sy, sz)] != me) continue;
-                double d[3];
-                lever_arm(bx, B, sx, sy, sz, d);
-                const float fin = fo[opp(i)] + bounce_shift(i, rw, B, d);
-                const double s = 2.0 * wgt(i) * a.rho0d + double(fo[opp(i)]) + double(fin);
-                const double dp[3] = {-cx(i) * s, -cy(i) * s, -cz(i) * s};
-                acc[0] += dp[0];
-                acc[1] += dp[1];
-                acc[2] += dp[2];
-                acc[3] += d[1] * dp[2] - d[2] * dp[1];
-                acc[4] += d[2] * dp[0] - d[0] * dp[2];
-                acc[5] += d[0] * dp[1] - d[1] * dp[0];
-            }
-        }
-        if (B.mode != 1) {
-            const uint16_t e = ev[c];
-            if ((e & 0xff) == me && (e & (EV_COVERED | EV_UNCOVERED))) {
-                double d[3], p[3];
-                lever_arm(bx, B, bc.x, bc.y, bc.z, d);
-                double sg;
-                if (e & EV_COVERED) {
-                    // the populations the body swallows (still in A)
-                    p[0] = p[1] = p[2] = 0.0;
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const double fi = S::ld(A[i * bx.stride + c], a.inv_scale);
-                        p[0] += cx(i) * fi;
-                        p[1] += cy(i) * fi;
-                        p[2] += cz(i) * fi;
-                    }
-                    sg = 1.0;
-                } else {
-                    // momentum of the refill, taken from the body
-                    const double rb = refill_density<S>(bx, A, own, ev, bc.x, bc.y, bc.z, a.rho0d, a.inv_scale);
-                    p[0] = rb * (B.v[0] + B.w[1] * d[2] - B.w[2] * d[1]);
-                    p[1] = rb * (B.v[1] + B.w[2] * d[0] - B.w[0] * d[2]);
-                    p[2] = rb * (B.v[2] + B.w[0] * d[1] - B.w[1] * d[0]);
-                    sg = -1.0;
-                }
-                acc[6] += sg * p[0];
-                acc[7] += sg * p[1];
-                acc[8] += sg * p[2];
-                acc[9] += sg * (d[1] * p[2] - d[2] * p[1]);
-                acc[10] += sg * (d[2] * p[0] - d[0] * p[2]);
-                acc[11] += sg * (d[0] * p[1] - d[1] * p[0]);
-            }
-        }
-    }
-    block_reduce<12>(acc, part + size_t(blockIdx.x) * 12);
-}
-
-// ---------------------------------------------------------------------------
-// the hot loop: pull streaming + bounce-back + TRT collision
+// the hot loop: every fluid cell without a body neighbour
 
 template <class S, bool AUDIT, bool FORCE>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(StepArgs a, const typename S::T *__restrict__ A,
                                                           typename S::T *__restrict__ Bf,
                                                           const uint8_t *__restrict__ own,
-                                                          const DevBody *__restrict__ bodies,
                                                           double *__restrict__ audit_part)
 {
-    const Box &bx = a.box;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
-    const uint64_t st = bx.stride;
-    const uint8_t o = idx < bx.n ? own[idx] : OWN_WALL;
+    const uint64_t st = a.box.stride;
+    const uint8_t o = idx < a.box.n ? own[idx] : OWN_WALL;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (is_fluid(o)) {
-        const uint32_t nx = bx.nx, ny = bx.ny, nz = bx.nz;
-        const uint32_t x = idx % nx, yz = idx / nx, y = yz % ny, z = yz / ny;
-        const uint32_t pl = nx * ny;
-        // unsigned offsets (mod 2^32) to the -1 / +1 neighbour on each axis
-        const uint32_t oxm = x == 0 ? nx - 1 : uint32_t(-1), oxp = x == nx - 1 ? uint32_t(1) - nx : 1u;
-        const uint32_t oym = y == 0 ? (ny - 1) * nx : uint32_t(0) - nx, oyp = y == ny - 1 ? uint32_t(0) - (ny - 1) * nx : nx;
-        const uint32_t ozm = z == 0 ? (nz - 1) * pl : uint32_t(0) - pl, ozp = z == nz - 1 ? uint32_t(0) - (nz - 1) * pl : pl;
-        auto src = [&](int i) -> uint32_t {
-            uint32_t s = idx;
-            if (cx(i) == 1) s += oxm;
-            else if (cx(i) == -1) s += oxp;
-            if (cy(i) == 1) s += oym;
-            else if (cy(i) == -1) s += oyp;
-            if (cz(i) == 1) s += ozm;
-            else if (cz(i) == -1) s += ozp;
-            return s;
-        };
+    if (o == OWN_FLUID || o == OWN_NB_WALL) {
+        const Nbr nb(a.box, idx);
         float f[Q];
         if (o == OWN_FLUID) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = S::ld(A[i * st + src(i)], a.inv_scale);
+            for (int i = 0; i < Q; ++i) f[i] = S::ld(A[i * st + nb.src(i)], a.inv_scale);
         } else {
-            float fo[Q];
-            float rw = 0.0f;
+            // no-slip walls: a population that would come from a wall is the
+            // cell's own opposite post-collision population
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                fo[i] = S::ld(A[i * st + idx], a.inv_scale);
-                rw += fo[i];
-            }
-            rw += a.rho0;
-            f[0] = fo[0];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const uint32_t s = src(i);
-                const uint8_t os = own[s];
-                if (is_fluid(os)) {
-                    f[i] = S::ld(A[i * st + s], a.inv_scale);
-                } else if (os == OWN_WALL) {
-                    f[i] = fo[opp(i)];
-                } else {
-                    double d[3];
-                    const DevBody &B = bodies[os - 1];
-                    lever_arm(bx, B, int(wrap(int(x) - cx(i), nx)), int(wrap(int(y) - cy(i), ny)),
-                              int(wrap(int(z) - cz(i), nz)), d);
-                    f[i] = fo[opp(i)] + bounce_shift(i, rw, B, d);
-                }
+                const uint32_t s = nb.src(i);
+                f[i] = is_fluid(own[s]) ? S::ld(A[i * st + s], a.inv_scale) : S::ld(A[opp(i) * st + idx], a.inv_scale);
             }
         }
-        // moments of the incoming deviations
-        float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            drho += f[i];
-            if (cx(i)) jx += cx(i) * f[i];
-            if (cy(i)) jy += cy(i) * f[i];
-            if (cz(i)) jz += cz(i) * f[i];
-        }
-        if (FORCE) {
-            jx += 0.5f * a.g[0];
-            jy += 0.5f * a.g[1];
-            jz += 0.5f * a.g[2];
-        }
-        const float rho = a.rho0 + drho;
-        const float ir = 1.0f / rho;
-        const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
-        const float usq = ux * ux + uy * uy + uz * uz;
-        const float le = a.lam_e, lo = a.lam_o;
-        float out[Q];
-        out[0] = f[0] - le * (f[0] - wgtf(0) * (drho - 1.5f * rho * usq));
-#pragma unroll
-        for (int i = 1; i < Q; i += 2) {
-            const int ib = i + 1;
-            const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-            const float ep = wgtf(i) * (drho + rho * (4.5f * cu * cu - 1.5f * usq));
-            const float em = wgtf(i) * rho * 3.0f * cu;
-            const float fp = 0.5f * (f[i] + f[ib]), fm = 0.5f * (f[i] - f[ib]);
-            const float de = le * (fp - ep), dodd = lo * (fm - em);
-            out[i] = f[i] - de - dodd;
-            out[ib] = f[ib] - de + dodd;
-        }
-        if (FORCE) {
-            const float ug = ux * a.g[0] + uy * a.g[1] + uz * a.g[2];
-            const float ce = 1.0f - 0.5f * le, co = 1.0f - 0.5f * lo;
-            out[0] += ce * wgtf(0) * (-3.0f * ug);
-#pragma unroll
-            for (int i = 1; i < Q; i += 2) {
-                const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-                const float cg = cx(i) * a.g[0] + cy(i) * a.g[1] + cz(i) * a.g[2];
-                const float se = wgtf(i) * (9.0f * cu * cg - 3.0f * ug);
-                const float so = 3.0f * wgtf(i) * cg;
-                out[i] += ce * se + co * so;
-                out[i + 1] += ce * se - co * so;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) Bf[i * st + idx] = S::st(out[i], a.scale);
-        if (AUDIT) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                // what was stored, as it will be read back
-                const double v = S::ld(S::st(out[i], a.scale), a.inv_scale);
-                am[0] += v;
-                am[1] += cx(i) * v;
-                am[2] += cy(i) * v;
-                am[3] += cz(i) * v;
-            }
-            am[4] = 1.0;
-        }
+        collide_store<S, AUDIT, FORCE>(a, f, Bf, idx, am);
     }
     if (AUDIT) block_reduce<5>(am, audit_part + size_t(blockIdx.x) * 5);
 }
 
 // ---------------------------------------------------------------------------
-// body update: reduce partials, WCA, symplectic Euler (one block)
+// rigid bodies
 
 __device__ void rotate_by(double e[3], const double w[3])
 {
@@ -434,88 +269,507 @@ __device__ void rotate_by(double e[3], const double w[3])
 
 __device__ double wca_magnitude(double r, double sigma, double eps)
 {
-    const double rc = pow(2.0, 1.0 / 6.0) * sigma;
+    const double rc = 1.122462048309373 * sigma;  // 2^(1/6) sigma
     if (r >= rc) return 0.0;
     if (r < 0.05 * sigma) r = 0.05 * sigma;
-    const double sr6 = pow(sigma / r, 6.0);
+    const double s2 = (sigma / r) * (sigma / r);
+    const double sr6 = s2 * s2 * s2;
     return 24.0 * eps / r * (2.0 * sr6 * sr6 - sr6);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_body(Box bx, DevBody *__restrict__ bodies, int nbody,
-                                                const int *__restrict__ start, const double *__restrict__ part,
-                                                double wca_sigma, double wca_eps, int *__restrict__ err)
+// State of body b at t+1 from its state at t, the step's integer force sums
+// q (NACC values) and WCA against every other body.
+__device__ void advance_body(const Box &bx, const DevBody *__restrict__ cur, int nbody, int b, const long long *q,
+                             double rho0, double sigma, double eps, DevBody &B, int *__restrict__ err)
 {
-    __shared__ double red[BLOCK][12];
-    __shared__ double tot[MAXB > 64 ? 64 : MAXB][12];
-    for (int b0 = 0; b0 < nbody; b0 += 64) {
-        const int bn = min(64, nbody - b0);
-        for (int bi = 0; bi < bn; ++bi) {
-            const int b = b0 + bi;
-            double acc[12];
-            for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-            for (int blk = start[b] + threadIdx.x; blk < start[b + 1]; blk += BLOCK)
-                for (int k = 0; k < 12; ++k) acc[k] += part[size_t(blk) * 12 + k];
-            for (int k = 0; k < 12; ++k) red[threadIdx.x][k] = acc[k];
-            __syncthreads();
-            for (int h = BLOCK / 2; h > 0; h >>= 1) {
-                if (threadIdx.x < h)
-                    for (int k = 0; k < 12; ++k) red[threadIdx.x][k] += red[threadIdx.x + h][k];
-                __syncthreads();
-            }
-            if (threadIdx.x < 12) tot[bi][threadIdx.x] = red[0][threadIdx.x];
-            __syncthreads();
-        }
-        if (threadIdx.x < bn) {
-            DevBody &B = bodies[b0 + threadIdx.x];
-            for (int k = 0; k < 3; ++k) {
-                B.Fbb[k] = tot[threadIdx.x][k];
-                B.Tbb[k] = tot[threadIdx.x][3 + k];
-                B.Fc[k] = tot[threadIdx.x][6 + k];
-                B.Tc[k] = tot[threadIdx.x][9 + k];
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
+    B = cur[b];
     const int nn[3] = {bx.nx, bx.ny, bx.nz};
-    for (int b = 0; b < nbody; ++b)
-        for (int k = 0; k < 3; ++k) bodies[b].Fwca[k] = 0.0;
-    for (int a = 0; a < nbody; ++a)
-        for (int b = a + 1; b < nbody; ++b) {
-            DevBody &A = bodies[a], &Bb = bodies[b];
-            double dv[3];
-            for (int k = 0; k < 3; ++k) dv[k] = min_image(Bb.pos[k] - A.pos[k], nn[k]);
-            const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-            const double fm = wca_magnitude(dist - A.R - Bb.R, wca_sigma, wca_eps);
-            if (fm == 0.0) continue;
-            for (int k = 0; k < 3; ++k) {
-                Bb.Fwca[k] += fm * dv[k] / dist;
-                A.Fwca[k] -= fm * dv[k] / dist;
-            }
-        }
-    for (int b = 0; b < nbody; ++b) {
-        DevBody &B = bodies[b];
+    double kf[3], kr[3], p[3];
+    for (int k = 0; k < 3; ++k) {
+        kf[k] = double(q[12 + k]);
+        kr[k] = double(q[15 + k]);
+        p[k] = B.pos[k] - floor(B.pos[k]);
+    }
+    const double pr = rho0 / 18.0;
+    const double pxk[3] = {p[1] * kf[2] - p[2] * kf[1], p[2] * kf[0] - p[0] * kf[2], p[0] * kf[1] - p[1] * kf[0]};
+    for (int k = 0; k < 3; ++k) {
+        B.Fbb[k] = double(q[k]) / FX_SCALE - pr * kf[k];
+        B.Tbb[k] = double(q[3 + k]) / FX_SCALE - pr * (0.5 * kr[k] - pxk[k]);
+        B.Fc[k] = double(q[6 + k]) / FX_SCALE;
+        B.Tc[k] = double(q[9 + k]) / FX_SCALE;
+        B.Fwca[k] = 0.0;
+    }
+    for (int j = 0; j < nbody; ++j) {
+        if (j == b) continue;
+        double dv[3];
+        for (int k = 0; k < 3; ++k) dv[k] = min_image(B.pos[k] - cur[j].pos[k], nn[k]);
+        const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        const double fm = wca_magnitude(dist - B.R - cur[j].R, sigma, eps);
+        if (fm == 0.0) continue;
+        for (int k = 0; k < 3; ++k) B.Fwca[k] += fm * dv[k] / dist;
+    }
+    for (int k = 0; k < 3; ++k) {
+        B.F[k] = B.Fbb[k] + B.Fc[k] + B.Fwca[k];
+        B.T[k] = B.Tbb[k] + B.Tc[k];
+    }
+    if (B.mode == 0) {
         for (int k = 0; k < 3; ++k) {
-            B.F[k] = B.Fbb[k] + B.Fc[k] + B.Fwca[k];
-            B.T[k] = B.Tbb[k] + B.Tc[k];
-        }
-        if (B.mode == 0) {
-            for (int k = 0; k < 3; ++k) {
-                B.v[k] += B.F[k] / B.m;
-                B.w[k] += B.T[k] / B.I;
-            }
-        }
-        if (B.mode == 0 || B.mode == 2) {
-            for (int k = 0; k < 3; ++k) {
-                if (!(fabs(B.v[k]) < 1.0)) err[2] = 1;
-                double p = B.pos[k] + B.v[k];
-                if (p >= nn[k]) p -= nn[k];
-                if (p < 0.0) p += nn[k];
-                B.pos[k] = p;
-            }
-            rotate_by(B.e, B.w);
+            B.v[k] += B.F[k] / B.m;
+            B.w[k] += B.T[k] / B.I;
         }
     }
+    if (B.mode == 0 || B.mode == 2) {
+        for (int k = 0; k < 3; ++k) {
+            if (!(fabs(B.v[k]) < 1.0)) err[2] = 1;
+            double x = B.pos[k] + B.v[k];
+            if (x >= nn[k]) x -= nn[k];
+            if (x < 0.0) x += nn[k];
+            // positions stay in [0, n) even after a flagged runaway
+            if (!(x >= 0.0 && x < nn[k])) x = 0.0;
+            B.pos[k] = x;
+        }
+        rotate_by(B.e, B.w);
+    }
+}
+
+// The step's integer sums of every body: the NCOPY copies of an
+// accumulator set added up into s_q[body][k] (integer sums, so every block
+// that calls this obtains the same values).
+__device__ void gather_sums(int nbody, const unsigned long long *__restrict__ acc, long long (*s_q)[NACC])
+{
+    for (int j = threadIdx.x; j < nbody * NACC; j += BLOCK) {
+        long long t = 0;
+#pragma unroll
+        for (int c = 0; c < NCOPY; ++c) t += static_cast<long long>(acc[c * (MAXB * NACC) + j]);
+        s_q[j / NACC][j % NACC] = t;
+    }
+    __syncthreads();
+}
+
+// Zero the first nbody entries of every copy of an accumulator set.
+__device__ __forceinline__ void clear_set(int nbody, unsigned long long *__restrict__ acc)
+{
+    for (int j = threadIdx.x; j < NCOPY * nbody * NACC; j += BLOCK) {
+        const int c = j / (nbody * NACC);
+        acc[c * (MAXB * NACC) + (j - c * nbody * NACC)] = 0ull;
+    }
+}
+
+// Body update by one block (used when no body moves, or when there are too
+// many bodies for every geometry block to repeat the update); also clears the
+// accumulator set of the step after next.
+__global__ __launch_bounds__(BLOCK) void k_body(Box bx, const DevBody *__restrict__ cur, DevBody *__restrict__ nxt,
+                                                int nbody, const unsigned long long *__restrict__ acc,
+                                                unsigned long long *__restrict__ acc_clear, double rho0, double sigma,
+                                                double eps, int *__restrict__ err)
+{
+    __shared__ long long s_q[MAXB][NACC];
+    gather_sums(nbody, acc, s_q);
+    for (int b = threadIdx.x; b < nbody; b += BLOCK) {
+        DevBody B;
+        advance_body(bx, cur, nbody, b, s_q[b], rho0, sigma, eps, B, err);
+        nxt[b] = B;
+    }
+    clear_set(nbody, acc_clear);
+}
+
+// ---------------------------------------------------------------------------
+// work layout of the boundary and geometry kernels: a block takes CPB
+// consecutive cells of one body's box (grown by g cells on each side), one
+// thread per (cell, direction); blocks [start[m], start[m+1]) belong to the
+// m-th listed body
+
+struct Slot {
+    int m;      // position in the body list
+    int cl, i;  // cell slot in the block, direction
+    int x, y, z;
+    bool valid;
+};
+
+template <class BT>
+__device__ __forceinline__ Slot slot_of(const Box &bx, const BT *bodies, const int *ids, const int *start, int nlist,
+                                        int g)
+{
+    Slot r;
+    r.cl = threadIdx.x / Q;
+    r.i = threadIdx.x - r.cl * Q;
+    const int blk = blockIdx.x;
+    int m = 0;
+    while (m + 1 < nlist && blk >= start[m + 1]) ++m;
+    r.m = m;
+    const BT &B = bodies[ids[m]];
+    const int side = 2 * (B.H + g) + 1;
+    const uint32_t l = uint32_t(blk - start[m]) * CPB + r.cl;
+    r.valid = r.cl < CPB && l < uint32_t(side) * side * side;
+    int o[3];
+    bbox_origin(B, o, g);
+    r.x = wrap(o[0] + int(l % side), bx.nx);
+    r.y = wrap(o[1] + int((l / side) % side), bx.ny);
+    r.z = wrap(o[2] + int(l / (side * side)), bx.nz);
+    return r;
+}
+
+// the lowest-listed body whose box contains the cell handles it, so every
+// cell is processed once
+template <class BT>
+__device__ __forceinline__ bool first_box(const Box &bx, const BT *bodies, const int *ids, int m, int x, int y, int z,
+                                          int g)
+{
+    for (int mm = 0; mm < m; ++mm)
+        if (in_bbox(bx, bodies[ids[mm]], x, y, z, g)) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// cells next to a body: moving-wall bounce-back and momentum exchange
+
+// The link of cell (x, y, z) in direction i whose source s = x - c_i is a
+// cell of body B: returns f_i^in = f_ibar*(x) + 6 w_i rho_w c_i.v_b, with the
+// wall velocity eq. (vb) plus the slip of eq. (squirmer) at the centre of s.
+// The momentum handed to the body, -c_i (f_ibar*(x) + f_i^in(x)), is split
+// into its small part (FP32 force and torque in fv) and the pressure part
+// -c_i 2 w_i rho0 (integer counts kf, kr).
+__device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int i, int x, int y, int z, float fob,
+                                           float rho_w, float (&fv)[6], int (&kf)[3], int (&kr)[3])
+{
+    const int c[3] = {rcx(i), rcy(i), rcz(i)};
+    const int k = i <= 6 ? 2 : 1;  // 36 w_i
+    const int sc[3] = {x - c[0], y - c[1], z - c[2]};
+    const int n[3] = {bx.nx, bx.ny, bx.nz};
+    int r[3];
+    float d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = wrap_small(sc[a] - (B.ip[a] - B.H), n[a]) - B.H;  // source relative to floor(pos)
+        d[a] = (float(r[a]) + 0.5f) - B.fr[a];
+    }
+    float vb[3] = {B.v[0] + B.w[1] * d[2] - B.w[2] * d[1], B.v[1] + B.w[2] * d[0] - B.w[0] * d[2],
+                   B.v[2] + B.w[0] * d[1] - B.w[1] * d[0]};
+    if (B.B1 != 0.0f) {
+        const float ir = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const float nn[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+        const float en = B.e[0] * nn[0] + B.e[1] * nn[1] + B.e[2] * nn[2];
+        const float am = B.B1 * (1.0f + B.beta * en);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vb[a] += am * (en * nn[a] - B.e[a]);
+    }
+    const float w = k == 2 ? 1.0f / 18.0f : 1.0f / 36.0f;
+    const float sh = 6.0f * w * rho_w * (c[0] * vb[0] + c[1] * vb[1] + c[2] * vb[2]);
+    const float fin = fob + sh;
+    const float var = fob + fin;
+    const float dp[3] = {-c[0] * var, -c[1] * var, -c[2] * var};
+    fv[0] = dp[0];
+    fv[1] = dp[1];
+    fv[2] = dp[2];
+    fv[3] = d[1] * dp[2] - d[2] * dp[1];
+    fv[4] = d[2] * dp[0] - d[0] * dp[2];
+    fv[5] = d[0] * dp[1] - d[1] * dp[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) kf[a] = k * c[a];
+    const int q[3] = {2 * r[0] + 1, 2 * r[1] + 1, 2 * r[2] + 1};
+    kr[0] = k * (q[1] * c[2] - q[2] * c[1]);
+    kr[1] = k * (q[2] * c[0] - q[0] * c[2]);
+    kr[2] = k * (q[0] * c[1] - q[1] * c[0]);
+    return fin;
+}
+
+// Every fluid cell with a body neighbour: pull streaming where the source is
+// fluid, reflection at walls, moving-wall bounce-back at bodies, then the
+// collision.  Momentum exchange: integer sums, reduced over the block for
+// the box's own body.
+template <class S, bool AUDIT, bool FORCE>
+__global__ __launch_bounds__(BLOCK) void k_boundary(StepArgs a, const typename S::T *__restrict__ A,
+                                                    typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
+                                                    const DevBody *__restrict__ cur,
+                                                    int nbody, const int *__restrict__ ids,
+                                                    const int *__restrict__ start, int nlist,
+                                                    unsigned long long *__restrict__ acc,
+                                                    double *__restrict__ audit_part)
+{
+    extern __shared__ double lds_dyn[];  // nbody LinkBody entries
+    LinkBody *lb = reinterpret_cast<LinkBody *>(lds_dyn);
+    __shared__ float s_fo[CPB][Q + 1];
+    __shared__ float s_fin[CPB][Q + 1];
+    const Box &bx = a.box;
+    const uint64_t st = bx.stride;
+    const Slot sl = slot_of(bx, cur, ids, start, nlist, 0);
+    const int i = sl.i;
+    const uint32_t c = cell_of(bx, sl.x, sl.y, sl.z);
+    const bool active = sl.valid && own[c] == OWN_NB_BODY && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 0);
+    const uint32_t s = cell_of(bx, wrap_small(sl.x - rcx(i), bx.nx), wrap_small(sl.y - rcy(i), bx.ny),
+                               wrap_small(sl.z - rcz(i), bx.nz));
+    float fa = 0.0f;
+    uint8_t os = OWN_FLUID;
+    if (active) {
+        s_fo[sl.cl][i] = S::ld(A[i * st + c], a.inv_scale);
+        fa = S::ld(A[i * st + s], a.inv_scale);
+        if (i > 0) os = own[s];
+    }
+    for (int b = threadIdx.x; b < nbody; b += BLOCK) {
+        const DevBody &D = cur[b];
+        LinkBody &L = lb[b];
+        for (int k = 0; k < 3; ++k) {
+            const double fl = floor(D.pos[k]);
+            L.ip[k] = int(fl);
+            L.fr[k] = float(D.pos[k] - fl);
+            L.v[k] = float(D.v[k]);
+            L.w[k] = float(D.w[k]);
+            L.e[k] = float(D.e[k]);
+        }
+        L.H = D.H;
+        L.B1 = float(D.B1);
+        L.beta = float(D.beta);
+    }
+    __syncthreads();
+    int key = -1;  // body of this thread's link
+    long long v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (active) {
+        float rw = 0.0f;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) rw += s_fo[sl.cl][j];
+        rw += a.rho0;
+        const float fob = s_fo[sl.cl][i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1)];
+        float fin;
+        if (is_fluid(os)) {
+            fin = fa;
+        } else if (os == OWN_WALL) {
+            fin = fob;
+        } else {
+            key = os - 1;
+            float fv[6];
+            int kf[3], kr[3];
+            fin = body_link(bx, lb[key], i, sl.x, sl.y, sl.z, fob, rw, fv, kf, kr);
+            for (int k = 0; k < 6; ++k) v[k] = to_fx(fv[k]);
+            for (int k = 0; k < 3; ++k) {
+                v[6 + k] = kf[k];
+                v[9 + k] = kr[k];
+            }
+        }
+        s_fin[sl.cl][i] = fin;
+    }
+    __syncthreads();
+    double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (active && i == 0) {
+        float f[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) f[j] = s_fin[sl.cl][j];
+        collide_store<S, AUDIT, FORCE>(a, f, Bf, c, am);
+    }
+    // links into the box's own body: reduced over the block, then one atomic
+    // per component into the block's copy of the sums (blocks without such a
+    // link skip this); links into another body (a cell touching two bodies)
+    // are added directly
+    constexpr int slot[12] = {0, 1, 2, 3, 4, 5, 12, 13, 14, 15, 16, 17};
+    unsigned long long *copy = acc + (blockIdx.x % NCOPY) * (MAXB * NACC);
+    const int home = ids[sl.m];
+    if (key >= 0 && key != home) {
+        for (int k = 0; k < 12; ++k) atomicAdd(&copy[key * NACC + slot[k]], static_cast<unsigned long long>(v[k]));
+        for (int k = 0; k < 12; ++k) v[k] = 0;
+    }
+    if (__syncthreads_or(key == home)) {
+        __shared__ long long s_sum[12];
+        block_reduce_i64<12>(v, s_sum);
+        if (threadIdx.x < 12)
+            atomicAdd(&copy[home * NACC + slot[threadIdx.x]], static_cast<unsigned long long>(s_sum[threadIdx.x]));
+    }
+    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blockIdx.x) * 5);
+}
+
+// ---------------------------------------------------------------------------
+// geometry and cell conversion at the new positions.  Owners of every cell
+// of the moving bodies' boxes are recomputed into the other owner buffer;
+// cells outside the boxes did not change and are equal in both buffers.
+
+// Inside test against a body staged in LDS: the same predicate as the
+// fixed-point test on absolute positions (cell centre minus rounded position,
+// minimum image, squared length <= Rq^2), evaluated relative to the floor of
+// the position, where the difference of a cell within the box needs no wrap
+// and fits 32 bits.
+__device__ __forceinline__ bool inside_geo(const Box &bx, const GeoBody &B, int x, int y, int z)
+{
+    const int c[3] = {x, y, z};
+    const int n[3] = {bx.nx, bx.ny, bx.nz};
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int r = wrap_small(c[k] - (B.ip[k] - B.H), n[k]) - B.H;
+        if (r < -B.H || r > B.H) return false;
+        const int D = (2 * r + 1) * (1 << 19) - B.pq[k];
+        sum += int64_t(D) * int64_t(D);
+    }
+    return sum <= B.Rq2;
+}
+
+// owner of cell (x, y, z) at the new positions, given its old owner
+// (static walls stay; first body that contains it; clash if two do)
+__device__ __forceinline__ uint8_t new_owner(const Box &bx, const GeoBody *gb, int nbody, uint8_t old, int x, int y,
+                                             int z, bool &clash)
+{
+    if (old == OWN_WALL) return OWN_WALL;
+    uint8_t nw = OWN_FLUID;
+    for (int b = 0; b < nbody; ++b) {
+        if (!inside_geo(bx, gb[b], x, y, z)) continue;
+        if (nw != OWN_FLUID) clash = true;
+        else nw = uint8_t(b + 1);
+    }
+    return nw;
+}
+
+// new body state in the form the inside test and the refill use
+__device__ __forceinline__ void stage_geo(const DevBody &D, GeoBody &G)
+{
+    for (int k = 0; k < 3; ++k) {
+        G.pos[k] = D.pos[k];
+        G.v[k] = D.v[k];
+        G.w[k] = D.w[k];
+        const double fl = floor(D.pos[k]);
+        G.ip[k] = int(fl);
+        G.pq[k] = int(__double2ll_rn(D.pos[k] * 1048576.0) - int64_t(fl) * 1048576);
+    }
+    G.Rq2 = D.Rq * D.Rq;
+    G.H = D.H;
+}
+
+// One thread per (cell, neighbour): the cells are those of the moving
+// bodies' boxes around their old positions (table cur), grown by one cell so
+// that they contain the boxes around the new positions (table nxt).
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_geoconv(StepArgs a, const DevBody *__restrict__ cur,
+                                                   DevBody *__restrict__ nxt, int nbody, int fused,
+                                                   const unsigned long long *__restrict__ acc_read,
+                                                   unsigned long long *__restrict__ acc_clear, double sigma,
+                                                   double eps, const int *__restrict__ ids,
+                                                   const int *__restrict__ start, int nlist,
+                                                   unsigned long long *__restrict__ acc_conv,
+                                                   const uint8_t *__restrict__ own_old, uint8_t *__restrict__ own_new,
+                                                   typename S::T *__restrict__ A, int *__restrict__ err)
+{
+    extern __shared__ double lds_dyn[];  // nbody GeoBody, then (fused) nbody x NACC sums
+    GeoBody *gb = reinterpret_cast<GeoBody *>(lds_dyn);
+    __shared__ uint8_t s_on[CPB][Q + 1], s_oo[CPB][Q + 1];
+    __shared__ double s_rho[CPB][Q + 1];
+    const Box &bx = a.box;
+    const uint64_t st = bx.stride;
+    const Slot sl = slot_of(bx, cur, ids, start, nlist, 1);
+    const int i = sl.i;
+    const bool mine = sl.valid && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 1);
+    // neighbour i of the cell (i = 0: the cell itself)
+    const int nxc = wrap_small(sl.x + rcx(i), bx.nx), nyc = wrap_small(sl.y + rcy(i), bx.ny),
+              nzc = wrap_small(sl.z + rcz(i), bx.nz);
+    const uint32_t ncell = cell_of(bx, nxc, nyc, nzc);
+    const uint8_t oo = mine ? own_old[ncell] : uint8_t(0);
+    // fused: every block advances the bodies itself (same values
+    // everywhere), block 0 publishes the new table and clears the set of the
+    // step after next; otherwise the new table is already in nxt
+    if (fused) {
+        long long (*s_q)[NACC] = reinterpret_cast<long long (*)[NACC]>(gb + nbody);
+        gather_sums(nbody, acc_read, s_q);
+        for (int b = threadIdx.x; b < nbody; b += BLOCK) {
+            DevBody D;
+            advance_body(bx, cur, nbody, b, s_q[b], a.rho0d, sigma, eps, D, err);
+            stage_geo(D, gb[b]);
+            if (blockIdx.x == 0) nxt[b] = D;
+        }
+        if (blockIdx.x == 0) clear_set(nbody, acc_clear);
+    } else {
+        for (int b = threadIdx.x; b < nbody; b += BLOCK) stage_geo(nxt[b], gb[b]);
+    }
+    __syncthreads();
+    bool clash = false;
+    if (mine) {
+        s_on[sl.cl][i] = new_owner(bx, gb, nbody, oo, nxc, nyc, nzc, clash);
+        s_oo[sl.cl][i] = oo;
+    }
+    __syncthreads();
+    if (mine) {
+        // densities of the neighbours that are fluid at both time levels,
+        // needed where the cell is uncovered
+        double r = -1.0;
+        const bool uncovered = is_body(s_oo[sl.cl][0]) && s_on[sl.cl][0] == OWN_FLUID;
+        if (uncovered && i > 0 && s_on[sl.cl][i] == OWN_FLUID && is_fluid(oo)) {
+            r = 0.0;
+            for (int j = 0; j < Q; ++j) r += double(S::ld(A[j * st + ncell], a.inv_scale));
+            r += a.rho0d;
+        }
+        s_rho[sl.cl][i] = r;
+    }
+    __syncthreads();
+    int key = -1;
+    long long fx[6] = {0, 0, 0, 0, 0, 0};
+    if (mine && i == 0) {
+        const uint32_t c = ncell;
+        const uint8_t old = oo, nw = s_on[sl.cl][0];
+        double p[3] = {0.0, 0.0, 0.0}, sg = 0.0;
+        int eb = -1;  // body of a conversion event
+        if (is_body(nw)) {
+            own_new[c] = nw;
+            if (is_fluid(old)) {
+                // covered: the body swallows the cell's populations
+                for (int j = 1; j < Q; ++j) {
+                    const double fj = S::ld(A[j * st + c], a.inv_scale);
+                    p[0] += rcx(j) * fj;
+                    p[1] += rcy(j) * fj;
+                    p[2] += rcz(j) * fj;
+                }
+                sg = 1.0;
+                eb = nw - 1;
+            }
+        } else if (nw == OWN_WALL) {
+            own_new[c] = OWN_WALL;
+        } else {
+            bool nb_body = false, nb_wall = false;
+            double rsum = 0.0;
+            int rcnt = 0;
+            for (int j = 1; j < Q; ++j) {
+                const uint8_t on = s_on[sl.cl][j];
+                nb_body |= is_body(on);
+                nb_wall |= on == OWN_WALL;
+                const double rj = s_rho[sl.cl][j];
+                if (rj >= 0.0) {
+                    rsum += rj;
+                    ++rcnt;
+                }
+            }
+            own_new[c] = nb_body ? OWN_NB_BODY : (nb_wall ? OWN_NB_WALL : OWN_FLUID);
+            if (is_body(old)) {
+                // uncovered: refill with f^eq(rho_bar, v + w x d); its
+                // momentum comes from the body that left
+                eb = old - 1;
+                const GeoBody &B = gb[eb];
+                double d[3], u[3];
+                lever_arm(bx, B, sl.x, sl.y, sl.z, d);
+                u[0] = B.v[0] + B.w[1] * d[2] - B.w[2] * d[1];
+                u[1] = B.v[1] + B.w[2] * d[0] - B.w[0] * d[2];
+                u[2] = B.v[2] + B.w[0] * d[1] - B.w[1] * d[0];
+                const double rb = rcnt ? rsum / rcnt : a.rho0d;
+                const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                for (int j = 0; j < Q; ++j) {
+                    const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
+                    const double w = j == 0 ? 1.0 / 3.0 : (j <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+                    const double dev = w * (rb - a.rho0d) + w * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                    A[j * st + c] = S::st(float(dev), a.scale);
+                }
+                p[0] = rb * u[0];
+                p[1] = rb * u[1];
+                p[2] = rb * u[2];
+                sg = -1.0;
+            }
+        }
+        if (eb >= 0) {
+            double d[3];
+            lever_arm(bx, gb[eb], sl.x, sl.y, sl.z, d);
+            key = eb;
+            fx[0] = to_fx(sg * p[0]);
+            fx[1] = to_fx(sg * p[1]);
+            fx[2] = to_fx(sg * p[2]);
+            fx[3] = to_fx(sg * (d[1] * p[2] - d[2] * p[1]));
+            fx[4] = to_fx(sg * (d[2] * p[0] - d[0] * p[2]));
+            fx[5] = to_fx(sg * (d[0] * p[1] - d[1] * p[0]));
+        }
+    }
+    if (clash) err[0] = 1;
+    constexpr int slot[6] = {6, 7, 8, 9, 10, 11};
+    if (__any(key >= 0)) wave_accumulate<6>(key, fx, slot, acc_conv + (blockIdx.x % NCOPY) * (MAXB * NACC));
 }
 
 // ---------------------------------------------------------------------------
@@ -528,10 +782,13 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Box bx, uint8_t *__restrict_
     const uint8_t o = own[c];
     if (!is_fluid(o)) return;
     const int x = c % bx.nx, y = (c / bx.nx) % bx.ny, z = c / (uint32_t(bx.nx) * bx.ny);
-    bool nb = false;
-    for (int i = 1; i < Q; ++i)
-        nb |= !is_fluid(own[cell_of(bx, wrap(x + cx(i), bx.nx), wrap(y + cy(i), bx.ny), wrap(z + cz(i), bx.nz))]);
-    own[c] = nb ? OWN_FLUID_NB : OWN_FLUID;
+    bool nb_body = false, nb_wall = false;
+    for (int i = 1; i < Q; ++i) {
+        const uint8_t on = own[cell_of(bx, wrap(x + cx(i), bx.nx), wrap(y + cy(i), bx.ny), wrap(z + cz(i), bx.nz))];
+        nb_body |= is_body(on);
+        nb_wall |= on == OWN_WALL;
+    }
+    own[c] = nb_body ? OWN_NB_BODY : (nb_wall ? OWN_NB_WALL : OWN_FLUID);
 }
 
 // mark (or, with check_only, test) the cells of body b
@@ -663,47 +920,53 @@ __global__ __launch_bounds__(BLOCK) void k_link_mask(Box bx, const uint8_t *__re
 // ---------------------------------------------------------------------------
 // host-side launchers (storage type resolved here)
 
+#define LB_TRY(x)                        \
+    do {                                 \
+        const hipError_t e_ = (x);       \
+        if (e_ != hipSuccess) return e_; \
+    } while (0)
+
 template <class S>
 static hipError_t launch_step_t(const StepLaunch &L)
 {
     using T = typename S::T;
     const StepArgs &a = L.args;
     const int nblk = int((a.box.n + BLOCK - 1) / BLOCK);
-    T *A = static_cast<T *>(L.A);
+    const T *A = static_cast<const T *>(L.A);
     T *B = static_cast<T *>(L.B);
-    if (L.nmov > 0) {
-        hipLaunchKernelGGL(k_geom, dim3(L.nblk_mov), dim3(BLOCK), 0, L.stream, a.box, L.bodies, L.nbody,
-                           L.mov_ids, L.mov_start, L.nmov, L.own, L.ev, L.err);
-        hipLaunchKernelGGL(k_refill<S>, dim3(L.nblk_mov), dim3(BLOCK), 0, L.stream, a, L.bodies, L.mov_ids,
-                           L.mov_start, L.nmov, L.own, L.ev, A);
-    }
-    if (L.nbody > 0)
-        hipLaunchKernelGGL(k_force<S>, dim3(L.nblk_all), dim3(BLOCK), 0, L.stream, a, L.bodies, L.all_ids,
-                           L.all_start, L.nbody, L.own, L.ev, A, L.part);
-    if (L.ev_start && hipEventRecord(L.ev_start, L.stream) != hipSuccess) return hipErrorUnknown;
     const bool force = a.g[0] != 0.0f || a.g[1] != 0.0f || a.g[2] != 0.0f;
-    if (L.audit) {
-        if (force)
-            hipLaunchKernelGGL((k_stream_collide<S, true, true>), dim3(nblk), dim3(BLOCK), 0, L.stream, a, A, B,
-                               L.own, L.bodies, L.audit_part);
-        else
-            hipLaunchKernelGGL((k_stream_collide<S, true, false>), dim3(nblk), dim3(BLOCK), 0, L.stream, a, A,
-                               B, L.own, L.bodies, L.audit_part);
-    } else {
-        if (force)
-            hipLaunchKernelGGL((k_stream_collide<S, false, true>), dim3(nblk), dim3(BLOCK), 0, L.stream, a, A,
-                               B, L.own, L.bodies, L.audit_part);
-        else
-            hipLaunchKernelGGL((k_stream_collide<S, false, false>), dim3(nblk), dim3(BLOCK), 0, L.stream, a, A,
-                               B, L.own, L.bodies, L.audit_part);
+    if (L.ev_start) LB_TRY(hipEventRecord(L.ev_start, L.stream));
+    auto k3 = L.audit ? (force ? k_stream_collide<S, true, true> : k_stream_collide<S, true, false>)
+                      : (force ? k_stream_collide<S, false, true> : k_stream_collide<S, false, false>);
+    hipLaunchKernelGGL(k3, dim3(nblk), dim3(BLOCK), 0, L.stream, a, A, B, L.own_cur, L.audit_part);
+    LB_TRY(hipGetLastError());
+    if (L.ev_stop) LB_TRY(hipEventRecord(L.ev_stop, L.stream));
+    int npart = nblk;
+    if (L.nbody > 0) {
+        auto kb = L.audit ? (force ? k_boundary<S, true, true> : k_boundary<S, true, false>)
+                          : (force ? k_boundary<S, false, true> : k_boundary<S, false, false>);
+        hipLaunchKernelGGL(kb, dim3(L.nblk_all), dim3(BLOCK), L.nbody * sizeof(LinkBody), L.stream, a, A, B,
+                           L.own_cur, L.bodies_cur, L.nbody, L.all_ids, L.all_start, L.nbody, L.acc_cur,
+                           L.audit_part + size_t(nblk) * 5);
+        LB_TRY(hipGetLastError());
+        npart += L.nblk_all;
     }
-    if (L.ev_stop && hipEventRecord(L.ev_stop, L.stream) != hipSuccess) return hipErrorUnknown;
-    if (L.audit)
-        hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, nblk, L.audit_out,
-                           L.err);
-    if (L.nbody > 0)
-        hipLaunchKernelGGL(k_body, dim3(1), dim3(BLOCK), 0, L.stream, a.box, L.bodies, L.nbody, L.all_start,
-                           L.part, L.wca_sigma, L.wca_eps, L.err);
+    if (L.audit) {
+        hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, npart, L.audit_out, L.err);
+        LB_TRY(hipGetLastError());
+    }
+    if (L.nbody == 0) return hipSuccess;
+    const int fused = L.nmov > 0 && L.nbody <= FUSE_MAX;
+    if (!fused) {
+        hipLaunchKernelGGL(k_body, dim3(1), dim3(BLOCK), 0, L.stream, a.box, L.bodies_cur, L.bodies_nxt, L.nbody,
+                           L.acc_cur, L.acc_clear, a.rho0d, L.wca_sigma, L.wca_eps, L.err);
+        LB_TRY(hipGetLastError());
+    }
+    if (L.nmov == 0) return hipSuccess;
+    const size_t lds = L.nbody * sizeof(GeoBody) + (fused ? L.nbody * NACC * sizeof(long long) : 0);
+    hipLaunchKernelGGL(k_geoconv<S>, dim3(L.nblk_mov), dim3(BLOCK), lds, L.stream, a, L.bodies_cur, L.bodies_nxt,
+                       L.nbody, fused, L.acc_cur, L.acc_clear, L.wca_sigma, L.wca_eps, L.mov_ids, L.mov_start,
+                       L.nmov, L.acc_conv, L.own_cur, L.own_nxt, B, L.err);
     return hipGetLastError();
 }
 

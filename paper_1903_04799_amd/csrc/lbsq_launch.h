@@ -16,22 +16,29 @@ struct StepArgs {
     double rho0d;
 };
 
+// Everything one time step t needs.  Buffers with _cur hold time t, those
+// with _nxt receive time t+1 (populations, owners, body table).  Force sums:
+// acc_cur collects this step's momentum exchange (and already holds the
+// conversion force of the previous move), acc_conv receives the conversion
+// force of this move, acc_clear is zeroed for the step after next.
 struct StepLaunch {
     StepArgs args;
-    void *A, *B;  // current and next population buffers
-    uint8_t *own;
-    uint16_t *ev;
-    DevBody *bodies;
+    const void *A;  // populations of time t
+    void *B;        // receives time t+1
+    const uint8_t *own_cur;
+    uint8_t *own_nxt;
+    const DevBody *bodies_cur;
+    DevBody *bodies_nxt;
     int nbody;
-    const int *mov_ids, *mov_start;  // moving bodies and their block ranges
-    int nmov, nblk_mov;
-    const int *all_ids, *all_start;  // all bodies and their block ranges
-    int nblk_all;
-    double *part, *audit_part, *audit_out;
+    const int *all_ids, *all_start;  // every body and the block ranges of its box
+    const int *mov_ids, *mov_start;  // moving bodies and theirs
+    int nblk_all, nmov, nblk_mov;  // blocks of CPB cells
+    unsigned long long *acc_cur, *acc_conv, *acc_clear;  // integer sum sets, ACCSET_SIZE each
+    double *audit_part, *audit_out;
     int *err;
     double wca_sigma, wca_eps;
     bool audit;
-    hipEvent_t ev_start, ev_stop;  // optional timing of the fused kernel
+    hipEvent_t ev_start, ev_stop;  // optional timing of the streaming kernel
     hipStream_t stream;
 };
 
