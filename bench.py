@@ -121,7 +121,7 @@ def main():
                    "n_fluid": f32["n_fluid"]},
         "roofline": {"bound": "hbm", "achieved": round(f32["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(f32["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_stream_collide", "kernel_us": round(f32["kernel_us"], 2),
+                     "kernel": "k_fluid", "kernel_us": round(f32["kernel_us"], 2),
                      "bytes_per_update": BYTES_PER_UPDATE["f32"]},
     }
     if not args.no_fp16:

@@ -195,8 +195,9 @@ int lb_save_state(lb_sim *s, void *buf, size_t bytes);
 int lb_load_state(lb_sim *s, const void *buf, size_t bytes);
 
 /* Kernel timing for measurement: when enabled, HIP events bracket every
- * launch of the fused stream-collide kernel; lb_kernel_time returns the
- * summed duration (ms) and launch count since it was enabled.             */
+ * launch of the fluid-update kernel (streaming, bounce-back and collision of
+ * every fluid cell); lb_kernel_time returns the summed duration (ms) and
+ * launch count since it was enabled.                                      */
 int lb_kernel_timing(lb_sim *s, int enable);
 int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches);
 

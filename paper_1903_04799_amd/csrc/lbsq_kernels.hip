@@ -1,17 +1,20 @@
 // lbsq_kernels.hip -- gfx950 kernels of the lattice Boltzmann squirmer library
 // (arXiv:1903.04799).
 //
-// A time step t is three launches on one stream:
-//   k_stream_collide  pull streaming and the TRT collision of eq. (lb) for
-//                     every fluid cell that has no body neighbour (static
-//                     walls are reflected in place): FP32 arithmetic on stored
-//                     deviations, A(t) -> B, non-temporal stores;
-//   k_boundary        the cells next to a body, found in the bodies' boxes:
-//                     the same update with moving-wall bounce-back carrying
+// A time step t is two launches on one stream:
+//   k_fluid           every fluid cell, A(t) -> B, FP32 arithmetic on stored
+//                     deviations, non-temporal stores.  Its leading blocks
+//                     take the cells next to a body, found in the bodies'
+//                     boxes, one thread per (cell, direction): pull streaming
+//                     and the TRT collision of eq. (lb) with moving-wall
+//                     bounce-back carrying
 //                     the rigid-body velocity eq. (vb) plus the squirmer slip
 //                     eq. (squirmer), and the momentum exchange of their
 //                     links, eqs. (bbforce), (bbtorque), accumulated as
-//                     fixed-point integers;
+//                     fixed-point integers.  The other blocks take every
+//                     remaining fluid cell, one thread per cell: pull
+//                     streaming and the collision (static walls reflected in
+//                     place);
 //   k_geoconv         the body update (decode of the integer force sums, WCA
 //                     eq. (wca), symplectic Euler), repeated by every block
 //                     when there are few bodies, else done before by the
@@ -221,12 +224,11 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&f
 // the hot loop: every fluid cell without a body neighbour
 
 template <class S, bool AUDIT, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void k_stream_collide(StepArgs a, const typename S::T *__restrict__ A,
-                                                          typename S::T *__restrict__ Bf,
-                                                          const uint8_t *__restrict__ own,
-                                                          double *__restrict__ audit_part)
+__device__ __forceinline__ void stream_collide_block(const StepArgs &a, const typename S::T *__restrict__ A,
+                                                     typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
+                                                     double *__restrict__ audit_part, uint32_t blk)
 {
-    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    const uint32_t idx = blk * BLOCK + threadIdx.x;
     const uint64_t st = a.box.stride;
     const uint8_t o = idx < a.box.n ? own[idx] : OWN_WALL;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(StepArgs a, const type
         }
         collide_store<S, AUDIT, FORCE>(a, f, Bf, idx, am);
     }
-    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blockIdx.x) * 5);
+    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,12 +390,11 @@ struct Slot {
 
 template <class BT>
 __device__ __forceinline__ Slot slot_of(const Box &bx, const BT *bodies, const int *ids, const int *start, int nlist,
-                                        int g)
+                                        int g, int blk)
 {
     Slot r;
     r.cl = threadIdx.x / Q;
     r.i = threadIdx.x - r.cl * Q;
-    const int blk = blockIdx.x;
     int m = 0;
     while (m + 1 < nlist && blk >= start[m + 1]) ++m;
     r.m = m;
@@ -478,13 +479,12 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
 // collision.  Momentum exchange: integer sums, reduced over the block for
 // the box's own body.
 template <class S, bool AUDIT, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void k_boundary(StepArgs a, const typename S::T *__restrict__ A,
-                                                    typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
-                                                    const DevBody *__restrict__ cur,
-                                                    int nbody, const int *__restrict__ ids,
-                                                    const int *__restrict__ start, int nlist,
-                                                    unsigned long long *__restrict__ acc,
-                                                    double *__restrict__ audit_part)
+__device__ __forceinline__ void boundary_block(const StepArgs &a, const typename S::T *__restrict__ A,
+                                               typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
+                                               const DevBody *__restrict__ cur, int nbody,
+                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
+                                               unsigned long long *__restrict__ acc,
+                                               double *__restrict__ audit_part, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody LinkBody entries
     LinkBody *lb = reinterpret_cast<LinkBody *>(lds_dyn);
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(BLOCK) void k_boundary(StepArgs a, const typename S
     __shared__ float s_fin[CPB][Q + 1];
     const Box &bx = a.box;
     const uint64_t st = bx.stride;
-    const Slot sl = slot_of(bx, cur, ids, start, nlist, 0);
+    const Slot sl = slot_of(bx, cur, ids, start, nlist, 0, blk);
     const int i = sl.i;
     const uint32_t c = cell_of(bx, sl.x, sl.y, sl.z);
     const bool active = sl.valid && own[c] == OWN_NB_BODY && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 0);
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void k_boundary(StepArgs a, const typename S
     // link skip this); links into another body (a cell touching two bodies)
     // are added directly
     constexpr int slot[12] = {0, 1, 2, 3, 4, 5, 12, 13, 14, 15, 16, 17};
-    unsigned long long *copy = acc + (blockIdx.x % NCOPY) * (MAXB * NACC);
+    unsigned long long *copy = acc + (blk % NCOPY) * (MAXB * NACC);
     const int home = ids[sl.m];
     if (key >= 0 && key != home) {
         for (int k = 0; k < 12; ++k) atomicAdd(&copy[key * NACC + slot[k]], static_cast<unsigned long long>(v[k]));
@@ -572,7 +572,27 @@ __global__ __launch_bounds__(BLOCK) void k_boundary(StepArgs a, const typename S
         if (threadIdx.x < 12)
             atomicAdd(&copy[home * NACC + slot[threadIdx.x]], static_cast<unsigned long long>(s_sum[threadIdx.x]));
     }
-    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blockIdx.x) * 5);
+    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
+}
+
+// The update of every fluid cell in one launch: the first nblk_b blocks take
+// the cells next to a body (listed first so that their longer latency
+// overlaps the streaming blocks), the rest stream and collide the remaining
+// cells, BLOCK consecutive cells per block.  Audit partials: streaming block
+// k writes slot k, boundary block k writes slot nblk_s + k.
+template <class S, bool AUDIT, bool FORCE>
+__global__ __launch_bounds__(BLOCK) void k_fluid(StepArgs a, const typename S::T *__restrict__ A,
+                                                 typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
+                                                 const DevBody *__restrict__ cur, int nbody,
+                                                 const int *__restrict__ ids, const int *__restrict__ start, int nblk_b,
+                                                 uint32_t nblk_s, unsigned long long *__restrict__ acc,
+                                                 double *__restrict__ audit_part)
+{
+    if (int(blockIdx.x) < nblk_b)
+        boundary_block<S, AUDIT, FORCE>(a, A, Bf, own, cur, nbody, ids, start, nbody, acc,
+                                        audit_part + size_t(nblk_s) * 5, blockIdx.x);
+    else
+        stream_collide_block<S, AUDIT, FORCE>(a, A, Bf, own, audit_part, blockIdx.x - uint32_t(nblk_b));
 }
 
 // ---------------------------------------------------------------------------
@@ -650,7 +670,7 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(StepArgs a, const DevBody *__
     __shared__ double s_rho[CPB][Q + 1];
     const Box &bx = a.box;
     const uint64_t st = bx.stride;
-    const Slot sl = slot_of(bx, cur, ids, start, nlist, 1);
+    const Slot sl = slot_of(bx, cur, ids, start, nlist, 1, blockIdx.x);
     const int i = sl.i;
     const bool mine = sl.valid && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 1);
     // neighbour i of the cell (i = 0: the cell itself)
@@ -936,21 +956,15 @@ static hipError_t launch_step_t(const StepLaunch &L)
     T *B = static_cast<T *>(L.B);
     const bool force = a.g[0] != 0.0f || a.g[1] != 0.0f || a.g[2] != 0.0f;
     if (L.ev_start) LB_TRY(hipEventRecord(L.ev_start, L.stream));
-    auto k3 = L.audit ? (force ? k_stream_collide<S, true, true> : k_stream_collide<S, true, false>)
-                      : (force ? k_stream_collide<S, false, true> : k_stream_collide<S, false, false>);
-    hipLaunchKernelGGL(k3, dim3(nblk), dim3(BLOCK), 0, L.stream, a, A, B, L.own_cur, L.audit_part);
+    auto kf = L.audit ? (force ? k_fluid<S, true, true> : k_fluid<S, true, false>)
+                      : (force ? k_fluid<S, false, true> : k_fluid<S, false, false>);
+    const int nblk_b = L.nbody > 0 ? L.nblk_all : 0;
+    hipLaunchKernelGGL(kf, dim3(uint32_t(nblk) + uint32_t(nblk_b)), dim3(BLOCK), L.nbody * sizeof(LinkBody), L.stream,
+                       a, A, B, L.own_cur, L.bodies_cur, L.nbody, L.all_ids, L.all_start, nblk_b, uint32_t(nblk),
+                       L.acc_cur, L.audit_part);
     LB_TRY(hipGetLastError());
     if (L.ev_stop) LB_TRY(hipEventRecord(L.ev_stop, L.stream));
-    int npart = nblk;
-    if (L.nbody > 0) {
-        auto kb = L.audit ? (force ? k_boundary<S, true, true> : k_boundary<S, true, false>)
-                          : (force ? k_boundary<S, false, true> : k_boundary<S, false, false>);
-        hipLaunchKernelGGL(kb, dim3(L.nblk_all), dim3(BLOCK), L.nbody * sizeof(LinkBody), L.stream, a, A, B,
-                           L.own_cur, L.bodies_cur, L.nbody, L.all_ids, L.all_start, L.nbody, L.acc_cur,
-                           L.audit_part + size_t(nblk) * 5);
-        LB_TRY(hipGetLastError());
-        npart += L.nblk_all;
-    }
+    const int npart = nblk + nblk_b;
     if (L.audit) {
         hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, npart, L.audit_out, L.err);
         LB_TRY(hipGetLastError());
