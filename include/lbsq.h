@@ -144,8 +144,14 @@ int lb_add_squirmer(lb_sim *s, const lb_squirmer *sq, int *id);
  * conversion.  Between steps the cell owners match the body positions.     */
 int lb_step(lb_sim *s, int nsteps);
 
-/* Advance several independent handles by nsteps each.  Every handle runs
- * on its own stream and gives the same result it would give alone.        */
+/* Advance n distinct handles by nsteps each, together: each step is one
+ * fluid launch and one geometry launch covering all of them, enqueued on the
+ * stream of sims[0] after the work already queued on every handle's stream
+ * (the other streams then wait for the batch).  Each handle gives the same
+ * result, bit for bit, that lb_step would give it alone.  Handles that
+ * cannot share a launch (different storage, a body force g, a fused audit,
+ * kernel timing, more than 8 bodies, more than 64 handles) are stepped one
+ * after the other instead.  LB_EINVAL if a handle is NULL or repeated.     */
 int lb_step_batch(lb_sim *const *sims, int n, int nsteps);
 
 /* Block until the handle's queued work is done; reports device errors.   */
@@ -203,6 +209,115 @@ int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches);
 
 int lb_destroy(lb_sim *s);
 const char *lb_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * Serving: a stream of independent squirmer simulations (requests) of
+ * different box sizes, radii and beta, kept resident in one device-memory
+ * arena and advanced together with continuous batching.
+ *
+ *   - Admission is first come, first served, while fewer than max_active
+ *     requests are resident and the next one fits in the arena of
+ *     budget_bytes; the rest wait in the queue.
+ *   - The resident requests advance in chunks of chunk_steps steps; each
+ *     step of a chunk is one batched fluid launch and one batched geometry
+ *     launch over all of them (captured once as a HIP graph per set of
+ *     resident requests when use_graph is set).  Requests join and leave
+ *     between chunks, so new arrivals overlap on the device with the work
+ *     already running, and a finished request's memory returns to the arena.
+ *   - Every request ends after exactly its nsteps steps with the result it
+ *     would have had as a handle of its own stepped by lb_step (same
+ *     kernels, bit for bit).
+ *   - Up to two chunks are queued on the device at a time; lb_server_progress
+ *     retires finished chunks, reads the results of the requests they
+ *     completed, admits queued requests and enqueues the next chunk.
+ * The server is not thread-safe.  Times are seconds on the server's clock
+ * (steady, from lb_server_create).                                        */
+
+enum { LB_REQ_MAXBODY = 8, LB_SERVER_MAXACTIVE = 64 };
+
+typedef struct lb_server lb_server;
+
+/* budget_bytes  device memory of the arena for resident requests (>= 2^20);
+ * max_active    resident requests at most, 1..64;
+ * chunk_steps   steps per chunk, 1..100000;
+ * use_graph     replay each chunk as a HIP graph (0: plain launches);
+ * storage, scale_log2, wca_sigma, wca_eps  as in lb_params, for every
+ *               request (nu comes with each request, rho0 = 1, magic 3/16);
+ * stream        hipStream_t of the batched steps (NULL: the server creates
+ *               a non-blocking stream).                                   */
+typedef struct lb_server_params {
+    size_t budget_bytes;
+    int max_active;
+    int chunk_steps;
+    int use_graph;
+    int storage, scale_log2;
+    double wca_sigma, wca_eps;
+    void *stream;
+} lb_server_params;
+
+/* One request: a periodic nx x ny x nz box at rest with viscosity nu and
+ * nbody (0..8) bodies, run for nsteps (>= 0) steps.  tag is handed back
+ * with the result.                                                        */
+typedef struct lb_request {
+    int nx, ny, nz;
+    double nu;
+    int nbody;
+    lb_squirmer body[LB_REQ_MAXBODY];
+    int64_t nsteps;
+    uint64_t tag;
+} lb_request;
+
+/* Result of a request: status LB_OK or the error that ended it (for example
+ * LB_EGEOM for overlapping bodies); body states and hydrodynamic force and
+ * torque after the last step (as lb_body_state and lb_force_torque); the
+ * FP64 fluid mass of the final state (lb_audit); the fluid cells at
+ * admission (the unit of the server's cell-update count); the server times
+ * of submission, admission and completion.                                */
+typedef struct lb_result {
+    uint64_t ticket, tag;
+    int status;
+    int nbody;
+    int64_t steps;
+    uint64_t fluid_cells;
+    double pos[LB_REQ_MAXBODY][3], e[LB_REQ_MAXBODY][3], v[LB_REQ_MAXBODY][3], w[LB_REQ_MAXBODY][3];
+    double F[LB_REQ_MAXBODY][3], T[LB_REQ_MAXBODY][3];
+    double mass;
+    double t_submit, t_admit, t_done;
+} lb_result;
+
+/* Counters since creation: lattice updates of fluid cells, chunks, graphs
+ * built, requests completed, and the arena's bytes in use now.            */
+typedef struct lb_server_stats {
+    uint64_t cell_updates;
+    uint64_t chunks;
+    uint64_t graphs;
+    uint64_t completed;
+    size_t arena_in_use;
+} lb_server_stats;
+
+/* LB_EINVAL for out-of-range parameters (checked before any device call),
+ * LB_ENOMEM if the arena cannot be allocated.                             */
+int lb_server_create(const lb_server_params *p, lb_server **out);
+
+/* Queue a request; *ticket (may be NULL) identifies its result.  LB_EINVAL
+ * for a malformed request, LB_EBUDGET if it can never fit in the arena.   */
+int lb_server_submit(lb_server *sv, const lb_request *rq, uint64_t *ticket);
+
+/* Retire finished chunks, admit, enqueue the next chunk; with wait != 0
+ * first block until the oldest queued chunk is done.  *active and *queued
+ * (may be NULL) receive the resident and waiting request counts.          */
+int lb_server_progress(lb_server *sv, int wait, int *active, int *queued);
+
+/* Move up to cap completed results to out (oldest first); *n receives how
+ * many.                                                                    */
+int lb_server_results(lb_server *sv, lb_result *out, int cap, int *n);
+
+int lb_server_stats_get(lb_server *sv, lb_server_stats *st);
+int lb_server_clock(lb_server *sv, double *t);
+
+/* Wait for the queued chunks, drop every request still resident or
+ * queued, and free the arena.                                             */
+int lb_server_destroy(lb_server *sv);
 
 #ifdef __cplusplus
 }

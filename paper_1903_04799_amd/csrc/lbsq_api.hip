@@ -6,36 +6,9 @@
 #include <new>
 #include <vector>
 
-#include "../../include/lbsq.h"
-#include "lbsq_launch.h"
+#include "lbsq_sim.h"
 
 using namespace lbsq;
-
-struct lb_sim {
-    lb_params p;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    StepArgs args{};
-    size_t esize = 4;
-    // double-buffered state; index cur holds the current time level
-    void *f[2] = {nullptr, nullptr};
-    uint8_t *own[2] = {nullptr, nullptr};
-    DevBody *d_bodies[2] = {nullptr, nullptr};
-    int cur = 0;
-    std::vector<DevBody> bodies;
-    int *d_lists = nullptr;  // mov_ids | mov_start | all_ids | all_start
-    int nmov = 0, nblk_mov = 0, nblk_all = 0;
-    unsigned long long *d_acc = nullptr;  // NACCSET sets of ACCSET_SIZE integer sums
-    size_t audit_blocks = 0;
-    double *d_audit_part = nullptr, *d_audit_out = nullptr;
-    int *d_err = nullptr;
-    int64_t steps = 0;
-    bool started = false, need_classify = true;
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-    double ms = 0.0;
-    int64_t launches = 0;
-};
 
 namespace {
 
@@ -98,6 +71,8 @@ int sync_check(lb_sim *s)
     return LB_OK;
 }
 
+int upload_desc(lb_sim *s);
+
 // Block ranges of the bodies' boxes (all bodies, and the moving ones).
 int rebuild_lists(lb_sim *s)
 {
@@ -130,41 +105,54 @@ int rebuild_lists(lb_sim *s)
         if (!s->d_audit_part) return LB_ENOMEM;
         s->audit_blocks = need;
     }
-    return LB_OK;
+    return upload_desc(s);
 }
 
-// the accumulator set that step number t writes its momentum exchange into
-unsigned long long *acc_set(lb_sim *s, int64_t t) { return s->d_acc + size_t(t % NACCSET) * ACCSET_SIZE; }
+}  // namespace
 
-void fill_launch(lb_sim *s, StepLaunch &L)
+// The step kernels' descriptor of a simulation, for time levels t = t0 + k.
+void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
 {
-    const int c = s->cur, n = 1 - s->cur;
-    L.args = s->args;
-    L.A = s->f[c];
-    L.B = s->f[n];
-    L.own_cur = s->own[c];
-    L.own_nxt = s->own[n];
-    L.bodies_cur = s->d_bodies[c];
-    L.bodies_nxt = s->d_bodies[n];
-    L.nbody = int(s->bodies.size());
-    L.mov_ids = s->d_lists;
-    L.mov_start = s->d_lists + s->nmov;
-    L.all_ids = s->d_lists + 2 * s->nmov + 1;
-    L.all_start = s->d_lists + 2 * s->nmov + 1 + L.nbody;
-    L.nmov = s->nmov;
-    L.nblk_mov = s->nblk_mov;
-    L.nblk_all = s->nblk_all;
-    L.acc_cur = acc_set(s, s->steps);
-    L.acc_conv = acc_set(s, s->steps + 1);
-    L.acc_clear = acc_set(s, s->steps + 2);
-    L.audit_part = s->d_audit_part;
-    L.audit_out = s->d_audit_out;
-    L.err = s->d_err;
-    L.wca_sigma = s->p.wca_sigma;
-    L.wca_eps = s->p.wca_eps;
-    L.audit = false;
-    L.ev_start = L.ev_stop = nullptr;
-    L.stream = s->stream;
+    std::memset(&d, 0, sizeof(d));
+    d.a = s->args;
+    for (int k = 0; k < 2; ++k) {
+        d.f[k] = s->f[k];
+        d.own[k] = s->own[k];
+        d.bodies[k] = s->d_bodies[k];
+    }
+    d.acc = s->d_acc;
+    d.nbody = int(s->bodies.size());
+    d.nmov = s->nmov;
+    d.mov_ids = s->d_lists;
+    d.mov_start = s->d_lists + s->nmov;
+    d.all_ids = s->d_lists + 2 * s->nmov + 1;
+    d.all_start = s->d_lists + 2 * s->nmov + 1 + d.nbody;
+    d.audit_part = s->d_audit_part;
+    d.err = s->d_err;
+    d.wca_sigma = s->p.wca_sigma;
+    d.wca_eps = s->p.wca_eps;
+    d.t0 = t0;
+    d.t_end = t_end;
+    d.nblk_b = d.nbody > 0 ? s->nblk_all : 0;
+    d.nblk_s = int((s->args.box.n + BLOCK - 1) / BLOCK);
+}
+
+// Blocks of the fluid and geometry launches of a simulation.
+void lbsq_sim_blocks(const lb_sim *s, uint32_t *fluid, uint32_t *geo)
+{
+    const int nbody = int(s->bodies.size());
+    *fluid = uint32_t((s->args.box.n + BLOCK - 1) / BLOCK) + uint32_t(nbody > 0 ? s->nblk_all : 0);
+    *geo = uint32_t(geo_blocks(nbody, s->nblk_mov));
+}
+
+namespace {
+
+// the standalone descriptor: k counts the simulation's own steps
+int upload_desc(lb_sim *s)
+{
+    SimDesc d;
+    lbsq_fill_desc(s, 0, INT64_MAX, d);
+    return hipMemcpy(s->d_desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess ? LB_OK : LB_EDEVICE;
 }
 
 int pull_bodies(lb_sim *s)
@@ -194,6 +182,19 @@ int classify_now(lb_sim *s)
 }
 
 }  // namespace
+
+void *lbsq_dev_alloc(lb_sim *s, size_t bytes) { return dev_alloc(s, bytes); }
+void lbsq_dev_free(lb_sim *s, void *p) { dev_free(s, p); }
+
+// Owner flags of the current buffer computed if pending; the handle counts
+// as started from then on.
+int lbsq_prepare(lb_sim *s)
+{
+    const int cl = classify_now(s);
+    if (cl != LB_OK) return cl;
+    s->started = true;
+    return LB_OK;
+}
 
 extern "C" {
 
@@ -227,6 +228,8 @@ int lb_destroy(lb_sim *s)
         dev_free(s, s->d_bodies[k]);
     }
     dev_free(s, s->d_lists);
+    dev_free(s, s->d_desc);
+    dev_free(s, s->d_batch_desc);
     dev_free(s, s->d_acc);
     dev_free(s, s->d_audit_part);
     dev_free(s, s->d_audit_out);
@@ -283,8 +286,9 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->audit_blocks = size_t(nblocks(n));
     s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
     s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
+    s->d_desc = static_cast<SimDesc *>(dev_alloc(s, sizeof(SimDesc)));
     if (!s->f[0] || !s->f[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
-        !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err) {
+        !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err || !s->d_desc) {
         lb_destroy(s);
         return LB_ENOMEM;
     }
@@ -295,7 +299,7 @@ int lb_create(const lb_params *p, lb_sim **out)
     if (e == hipSuccess) e = hipMemsetAsync(s->own[1], 0, n, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, NERR * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) {
+    if (e != hipSuccess || upload_desc(s) != LB_OK) {
         lb_destroy(s);
         return LB_EDEVICE;
     }
@@ -380,10 +384,23 @@ int lb_step(lb_sim *s, int nsteps)
     const int cl = classify_now(s);
     if (cl != LB_OK) return cl;
     s->started = true;
+    BatchLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.desc = s->d_desc;
+    L.map.nsim = 1;
+    lbsq_sim_blocks(s, &L.map.fluid0[1], &L.map.geo0[1]);
+    L.nbody_max = int(s->bodies.size());
+    L.force = s->args.g[0] != 0.0f || s->args.g[1] != 0.0f || s->args.g[2] != 0.0f;
+    L.audit_part = s->d_audit_part;
+    L.audit_out = s->d_audit_out;
+    L.npart = int(L.map.fluid0[1]);
+    L.err = s->d_err;
+    L.body_kernel = L.nbody_max > FUSE_MAX;
+    L.stream = s->stream;
     for (int t = 0; t < nsteps; ++t) {
-        StepLaunch L;
-        fill_launch(s, L);
+        L.k = s->steps;
         L.audit = s->p.audit_every > 0 && ((s->steps + 1) % s->p.audit_every == 0);
+        L.ev_start = L.ev_stop = nullptr;
         if (s->timing) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return LB_EDEVICE;
@@ -391,21 +408,9 @@ int lb_step(lb_sim *s, int nsteps)
             L.ev_start = a;
             L.ev_stop = b;
         }
-        if (launch_step(s->p.storage, L) != hipSuccess) return LB_EDEVICE;
+        if (launch_batch_step(s->p.storage, L) != hipSuccess) return LB_EDEVICE;
         s->cur ^= 1;
         s->steps++;
-    }
-    return LB_OK;
-}
-
-int lb_step_batch(lb_sim *const *sims, int n, int nsteps)
-{
-    if ((!sims && n > 0) || n < 0 || nsteps < 0) return LB_EINVAL;
-    for (int k = 0; k < n; ++k)
-        if (!sims[k]) return LB_EINVAL;
-    for (int k = 0; k < n; ++k) {
-        const int rc = lb_step(sims[k], nsteps);
-        if (rc != LB_OK) return rc;
     }
     return LB_OK;
 }
@@ -672,6 +677,7 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     int st = sync_check(s);
     if (st != LB_OK) return st;
     const char *p = static_cast<const char *>(buf) + sizeof(h);
+    s->cur = int(h.steps & 1);
     if (hipMemcpy(s->f[s->cur], p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
     for (int k = 0; k < 2; ++k)

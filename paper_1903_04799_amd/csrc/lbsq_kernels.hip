@@ -1,7 +1,8 @@
 // lbsq_kernels.hip -- gfx950 kernels of the lattice Boltzmann squirmer library
 // (arXiv:1903.04799).
 //
-// A time step t is two launches on one stream:
+// A time step t is two launches on one stream, each covering every
+// simulation of a batch (one simulation is a batch of one):
 //   k_fluid           every fluid cell, A(t) -> B, FP32 arithmetic on stored
 //                     deviations, non-temporal stores.  Its leading blocks
 //                     take the cells next to a body, found in the bodies'
@@ -357,22 +358,37 @@ __device__ __forceinline__ void clear_set(int nbody, unsigned long long *__restr
     }
 }
 
-// Body update by one block (used when no body moves, or when there are too
-// many bodies for every geometry block to repeat the update); also clears the
-// accumulator set of the step after next.
-__global__ __launch_bounds__(BLOCK) void k_body(Box bx, const DevBody *__restrict__ cur, DevBody *__restrict__ nxt,
-                                                int nbody, const unsigned long long *__restrict__ acc,
-                                                unsigned long long *__restrict__ acc_clear, double rho0, double sigma,
-                                                double eps, int *__restrict__ err)
+// the accumulator set of step t
+__device__ __forceinline__ unsigned long long *acc_set(unsigned long long *acc, int64_t t)
+{
+    return acc + size_t(t % NACCSET) * ACCSET_SIZE;
+}
+
+// Body update of one simulation (descriptor D[0]) by one block, for more
+// bodies than every geometry block can repeat the update for; also clears
+// the accumulator set of the step after next.
+__global__ __launch_bounds__(BLOCK) void k_body(const SimDesc *__restrict__ D, int64_t k)
 {
     __shared__ long long s_q[MAXB][NACC];
-    gather_sums(nbody, acc, s_q);
-    for (int b = threadIdx.x; b < nbody; b += BLOCK) {
+    const SimDesc &d = D[0];
+    const int64_t t = d.t0 + k;
+    if (t >= d.t_end) return;
+    const int c = int(t & 1);
+    gather_sums(d.nbody, acc_set(d.acc, t), s_q);
+    for (int b = threadIdx.x; b < d.nbody; b += BLOCK) {
         DevBody B;
-        advance_body(bx, cur, nbody, b, s_q[b], rho0, sigma, eps, B, err);
-        nxt[b] = B;
+        advance_body(d.a.box, d.bodies[c], d.nbody, b, s_q[b], d.a.rho0d, d.wca_sigma, d.wca_eps, B, d.err);
+        d.bodies[c ^ 1][b] = B;
     }
-    clear_set(nbody, acc_clear);
+    clear_set(d.nbody, acc_set(d.acc, t + 2));
+}
+
+// the simulation of a batched launch that block blk belongs to
+__device__ __forceinline__ int find_sim(const uint32_t *start, int nsim, uint32_t blk)
+{
+    int s = 0;
+    while (s + 1 < nsim && blk >= start[s + 1]) ++s;
+    return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -575,24 +591,29 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, const typename
     if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
 }
 
-// The update of every fluid cell in one launch: the first nblk_b blocks take
-// the cells next to a body (listed first so that their longer latency
+// The update of every fluid cell of every simulation of a batch, one launch
+// per step.  A simulation's blocks are contiguous; its first nblk_b blocks
+// take the cells next to a body (listed first so that their longer latency
 // overlaps the streaming blocks), the rest stream and collide the remaining
 // cells, BLOCK consecutive cells per block.  Audit partials: streaming block
-// k writes slot k, boundary block k writes slot nblk_s + k.
+// j writes slot j, boundary block j writes slot nblk_s + j.
 template <class S, bool AUDIT, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void k_fluid(StepArgs a, const typename S::T *__restrict__ A,
-                                                 typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
-                                                 const DevBody *__restrict__ cur, int nbody,
-                                                 const int *__restrict__ ids, const int *__restrict__ start, int nblk_b,
-                                                 uint32_t nblk_s, unsigned long long *__restrict__ acc,
-                                                 double *__restrict__ audit_part)
+__global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, BatchMap m, int64_t k)
 {
-    if (int(blockIdx.x) < nblk_b)
-        boundary_block<S, AUDIT, FORCE>(a, A, Bf, own, cur, nbody, ids, start, nbody, acc,
-                                        audit_part + size_t(nblk_s) * 5, blockIdx.x);
+    using T = typename S::T;
+    const int si = find_sim(m.fluid0, m.nsim, blockIdx.x);
+    const SimDesc &d = D[si];
+    const int64_t t = d.t0 + k;
+    if (t >= d.t_end) return;
+    const int c = int(t & 1);
+    const T *A = static_cast<const T *>(d.f[c]);
+    T *B = static_cast<T *>(d.f[c ^ 1]);
+    const int blk = int(blockIdx.x - m.fluid0[si]);
+    if (blk < d.nblk_b)
+        boundary_block<S, AUDIT, FORCE>(d.a, A, B, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
+                                        acc_set(d.acc, t), d.audit_part + size_t(d.nblk_s) * 5, blk);
     else
-        stream_collide_block<S, AUDIT, FORCE>(a, A, Bf, own, audit_part, blockIdx.x - uint32_t(nblk_b));
+        stream_collide_block<S, AUDIT, FORCE>(d.a, A, B, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
 }
 
 // ---------------------------------------------------------------------------
@@ -653,24 +674,48 @@ __device__ __forceinline__ void stage_geo(const DevBody &D, GeoBody &G)
 // One thread per (cell, neighbour): the cells are those of the moving
 // bodies' boxes around their old positions (table cur), grown by one cell so
 // that they contain the boxes around the new positions (table nxt).
+// Fused body update: every block advances the bodies itself (the same
+// values everywhere) into gb; block 0 publishes the new table and clears the
+// accumulator set of the step after next.
+__device__ __forceinline__ void update_bodies_in_block(const StepArgs &a, const DevBody *__restrict__ cur,
+                                                       DevBody *__restrict__ nxt, int nbody,
+                                                       const unsigned long long *__restrict__ acc_read,
+                                                       unsigned long long *__restrict__ acc_clear, double sigma,
+                                                       double eps, int *__restrict__ err, GeoBody *gb, int blk)
+{
+    long long (*s_q)[NACC] = reinterpret_cast<long long (*)[NACC]>(gb + nbody);
+    gather_sums(nbody, acc_read, s_q);
+    for (int b = threadIdx.x; b < nbody; b += BLOCK) {
+        DevBody D;
+        advance_body(a.box, cur, nbody, b, s_q[b], a.rho0d, sigma, eps, D, err);
+        stage_geo(D, gb[b]);
+        if (blk == 0) nxt[b] = D;
+    }
+    if (blk == 0) clear_set(nbody, acc_clear);
+}
+
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_geoconv(StepArgs a, const DevBody *__restrict__ cur,
-                                                   DevBody *__restrict__ nxt, int nbody, int fused,
-                                                   const unsigned long long *__restrict__ acc_read,
-                                                   unsigned long long *__restrict__ acc_clear, double sigma,
-                                                   double eps, const int *__restrict__ ids,
-                                                   const int *__restrict__ start, int nlist,
-                                                   unsigned long long *__restrict__ acc_conv,
-                                                   const uint8_t *__restrict__ own_old, uint8_t *__restrict__ own_new,
-                                                   typename S::T *__restrict__ A, int *__restrict__ err)
+__device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *__restrict__ cur,
+                                              DevBody *__restrict__ nxt, int nbody, bool fused,
+                                              const unsigned long long *__restrict__ acc_read,
+                                              unsigned long long *__restrict__ acc_clear, double sigma, double eps,
+                                              const int *__restrict__ ids, const int *__restrict__ start, int nlist,
+                                              unsigned long long *__restrict__ acc_conv,
+                                              const uint8_t *__restrict__ own_old, uint8_t *__restrict__ own_new,
+                                              typename S::T *__restrict__ A, int *__restrict__ err, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody GeoBody, then (fused) nbody x NACC sums
     GeoBody *gb = reinterpret_cast<GeoBody *>(lds_dyn);
     __shared__ uint8_t s_on[CPB][Q + 1], s_oo[CPB][Q + 1];
     __shared__ double s_rho[CPB][Q + 1];
+    if (nlist == 0) {
+        // no moving body: the single block only updates the bodies
+        if (fused) update_bodies_in_block(a, cur, nxt, nbody, acc_read, acc_clear, sigma, eps, err, gb, blk);
+        return;
+    }
     const Box &bx = a.box;
     const uint64_t st = bx.stride;
-    const Slot sl = slot_of(bx, cur, ids, start, nlist, 1, blockIdx.x);
+    const Slot sl = slot_of(bx, cur, ids, start, nlist, 1, blk);
     const int i = sl.i;
     const bool mine = sl.valid && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 1);
     // neighbour i of the cell (i = 0: the cell itself)
@@ -682,15 +727,7 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(StepArgs a, const DevBody *__
     // everywhere), block 0 publishes the new table and clears the set of the
     // step after next; otherwise the new table is already in nxt
     if (fused) {
-        long long (*s_q)[NACC] = reinterpret_cast<long long (*)[NACC]>(gb + nbody);
-        gather_sums(nbody, acc_read, s_q);
-        for (int b = threadIdx.x; b < nbody; b += BLOCK) {
-            DevBody D;
-            advance_body(bx, cur, nbody, b, s_q[b], a.rho0d, sigma, eps, D, err);
-            stage_geo(D, gb[b]);
-            if (blockIdx.x == 0) nxt[b] = D;
-        }
-        if (blockIdx.x == 0) clear_set(nbody, acc_clear);
+        update_bodies_in_block(a, cur, nxt, nbody, acc_read, acc_clear, sigma, eps, err, gb, blk);
     } else {
         for (int b = threadIdx.x; b < nbody; b += BLOCK) stage_geo(nxt[b], gb[b]);
     }
@@ -789,7 +826,23 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(StepArgs a, const DevBody *__
     }
     if (clash) err[0] = 1;
     constexpr int slot[6] = {6, 7, 8, 9, 10, 11};
-    if (__any(key >= 0)) wave_accumulate<6>(key, fx, slot, acc_conv + (blockIdx.x % NCOPY) * (MAXB * NACC));
+    if (__any(key >= 0)) wave_accumulate<6>(key, fx, slot, acc_conv + (blk % NCOPY) * (MAXB * NACC));
+}
+
+// Geometry and conversion of every simulation of a batch, one launch per
+// step (blocks of a simulation contiguous).
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D, BatchMap m, int64_t k)
+{
+    const int si = find_sim(m.geo0, m.nsim, blockIdx.x);
+    const SimDesc &d = D[si];
+    const int64_t t = d.t0 + k;
+    if (t >= d.t_end) return;
+    const int c = int(t & 1);
+    geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.nbody <= FUSE_MAX, acc_set(d.acc, t),
+                     acc_set(d.acc, t + 2), d.wca_sigma, d.wca_eps, d.mov_ids, d.mov_start, d.nmov,
+                     acc_set(d.acc, t + 1), d.own[c], d.own[c ^ 1], static_cast<typename S::T *>(d.f[c ^ 1]), d.err,
+                     int(blockIdx.x - m.geo0[si]));
 }
 
 // ---------------------------------------------------------------------------
@@ -947,49 +1000,44 @@ __global__ __launch_bounds__(BLOCK) void k_link_mask(Box bx, const uint8_t *__re
     } while (0)
 
 template <class S>
-static hipError_t launch_step_t(const StepLaunch &L)
+static hipError_t launch_batch_t(const BatchLaunch &L)
 {
-    using T = typename S::T;
-    const StepArgs &a = L.args;
-    const int nblk = int((a.box.n + BLOCK - 1) / BLOCK);
-    const T *A = static_cast<const T *>(L.A);
-    T *B = static_cast<T *>(L.B);
-    const bool force = a.g[0] != 0.0f || a.g[1] != 0.0f || a.g[2] != 0.0f;
+    const BatchMap &m = L.map;
+    const uint32_t nf = m.fluid0[m.nsim], ng = m.geo0[m.nsim];
     if (L.ev_start) LB_TRY(hipEventRecord(L.ev_start, L.stream));
-    auto kf = L.audit ? (force ? k_fluid<S, true, true> : k_fluid<S, true, false>)
-                      : (force ? k_fluid<S, false, true> : k_fluid<S, false, false>);
-    const int nblk_b = L.nbody > 0 ? L.nblk_all : 0;
-    hipLaunchKernelGGL(kf, dim3(uint32_t(nblk) + uint32_t(nblk_b)), dim3(BLOCK), L.nbody * sizeof(LinkBody), L.stream,
-                       a, A, B, L.own_cur, L.bodies_cur, L.nbody, L.all_ids, L.all_start, nblk_b, uint32_t(nblk),
-                       L.acc_cur, L.audit_part);
-    LB_TRY(hipGetLastError());
+    if (nf > 0) {
+        auto kf = L.audit ? (L.force ? k_fluid<S, true, true> : k_fluid<S, true, false>)
+                          : (L.force ? k_fluid<S, false, true> : k_fluid<S, false, false>);
+        hipLaunchKernelGGL(kf, dim3(nf), dim3(BLOCK), size_t(L.nbody_max) * sizeof(LinkBody), L.stream, L.desc, m,
+                           L.k);
+        LB_TRY(hipGetLastError());
+    }
     if (L.ev_stop) LB_TRY(hipEventRecord(L.ev_stop, L.stream));
-    const int npart = nblk + nblk_b;
     if (L.audit) {
-        hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, npart, L.audit_out, L.err);
+        hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, L.npart, L.audit_out,
+                           L.err);
         LB_TRY(hipGetLastError());
     }
-    if (L.nbody == 0) return hipSuccess;
-    const int fused = L.nmov > 0 && L.nbody <= FUSE_MAX;
-    if (!fused) {
-        hipLaunchKernelGGL(k_body, dim3(1), dim3(BLOCK), 0, L.stream, a.box, L.bodies_cur, L.bodies_nxt, L.nbody,
-                           L.acc_cur, L.acc_clear, a.rho0d, L.wca_sigma, L.wca_eps, L.err);
+    if (L.body_kernel) {
+        hipLaunchKernelGGL(k_body, dim3(1), dim3(BLOCK), 0, L.stream, L.desc, L.k);
         LB_TRY(hipGetLastError());
     }
-    if (L.nmov == 0) return hipSuccess;
-    const size_t lds = L.nbody * sizeof(GeoBody) + (fused ? L.nbody * NACC * sizeof(long long) : 0);
-    hipLaunchKernelGGL(k_geoconv<S>, dim3(L.nblk_mov), dim3(BLOCK), lds, L.stream, a, L.bodies_cur, L.bodies_nxt,
-                       L.nbody, fused, L.acc_cur, L.acc_clear, L.wca_sigma, L.wca_eps, L.mov_ids, L.mov_start,
-                       L.nmov, L.acc_conv, L.own_cur, L.own_nxt, B, L.err);
-    return hipGetLastError();
+    if (ng > 0) {
+        // staged bodies, plus the sums of a fused body update (at most FUSE_MAX bodies)
+        const size_t lds = size_t(L.nbody_max) * sizeof(GeoBody) +
+                           size_t(L.nbody_max < FUSE_MAX ? L.nbody_max : FUSE_MAX) * NACC * sizeof(long long);
+        hipLaunchKernelGGL(k_geoconv<S>, dim3(ng), dim3(BLOCK), lds, L.stream, L.desc, m, L.k);
+        LB_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_step(int storage, const StepLaunch &L)
+hipError_t launch_batch_step(int storage, const BatchLaunch &L)
 {
     switch (storage) {
-    case 1: return launch_step_t<StF16>(L);
-    case 2: return launch_step_t<StBF16>(L);
-    default: return launch_step_t<StF32>(L);
+    case 1: return launch_batch_t<StF16>(L);
+    case 2: return launch_batch_t<StBF16>(L);
+    default: return launch_batch_t<StF32>(L);
     }
 }
 

@@ -16,33 +16,68 @@ struct StepArgs {
     double rho0d;
 };
 
-// Everything one time step t needs.  Buffers with _cur hold time t, those
-// with _nxt receive time t+1 (populations, owners, body table).  Force sums:
-// acc_cur collects this step's momentum exchange (and already holds the
-// conversion force of the previous move), acc_conv receives the conversion
-// force of this move, acc_clear is zeroed for the step after next.
-struct StepLaunch {
-    StepArgs args;
-    const void *A;  // populations of time t
-    void *B;        // receives time t+1
-    const uint8_t *own_cur;
-    uint8_t *own_nxt;
-    const DevBody *bodies_cur;
-    DevBody *bodies_nxt;
-    int nbody;
-    const int *all_ids, *all_start;  // every body and the block ranges of its box
-    const int *mov_ids, *mov_start;  // moving bodies and theirs
-    int nblk_all, nmov, nblk_mov;  // blocks of CPB cells
-    unsigned long long *acc_cur, *acc_conv, *acc_clear;  // integer sum sets, ACCSET_SIZE each
-    double *audit_part, *audit_out;
+// Most simulations one batched launch can take.
+constexpr int MAXSIM = 64;
+
+// One simulation as the step kernels see it.  The kernels of step k of a
+// launch sequence advance time level t = t0 + k, read from buffers [t & 1]
+// and written to buffers [(t & 1) ^ 1]; steps with t >= t_end are skipped.
+// Force sums: set t % 3 collects step t's momentum exchange (and already
+// holds the conversion force of the previous move), set (t+1) % 3 receives
+// the conversion force of this move, set (t+2) % 3 is zeroed.
+struct SimDesc {
+    StepArgs a;
+    void *f[2];
+    uint8_t *own[2];
+    DevBody *bodies[2];
+    unsigned long long *acc;  // NACCSET sets of ACCSET_SIZE integers
+    const int *mov_ids, *mov_start;  // moving bodies and the block ranges of their boxes
+    const int *all_ids, *all_start;  // every body and theirs
+    double *audit_part;
     int *err;
     double wca_sigma, wca_eps;
-    bool audit;
-    hipEvent_t ev_start, ev_stop;  // optional timing of the streaming kernel
+    int64_t t0, t_end;
+    int nbody, nmov;
+    int nblk_b, nblk_s;  // boundary and streaming blocks of the fluid launch
+};
+
+// Block ranges of the simulations of a batched launch: simulation j owns
+// blocks [fluid0[j], fluid0[j+1]) of the fluid launch and [geo0[j],
+// geo0[j+1]) of the geometry launch.
+struct BatchMap {
+    int nsim;
+    uint32_t fluid0[MAXSIM + 1];
+    uint32_t geo0[MAXSIM + 1];
+};
+
+// One step of a batch: the fluid launch, then (one simulation only) the
+// audit reduction and the one-block body update, then the geometry launch.
+struct BatchLaunch {
+    const SimDesc *desc;  // device array of map.nsim descriptors
+    BatchMap map;
+    int64_t k;
+    int nbody_max;        // most bodies of any simulation (LDS size)
+    bool force;           // a body force g is set (one simulation only)
+    bool audit;           // fused audit (one simulation only)
+    double *audit_part, *audit_out;
+    int npart;
+    int *err;
+    bool body_kernel;     // body update by k_body (one simulation only)
+    hipEvent_t ev_start, ev_stop;  // optional timing of the fluid launch
     hipStream_t stream;
 };
 
-hipError_t launch_step(int storage, const StepLaunch &L);
+// Geometry blocks of a simulation: none without bodies; with at most
+// FUSE_MAX bodies at least one (it carries the body update); else those of
+// the moving bodies' boxes.
+inline int geo_blocks(int nbody, int nblk_mov)
+{
+    if (nbody == 0) return 0;
+    if (nbody <= FUSE_MAX) return nblk_mov > 0 ? nblk_mov : 1;
+    return nblk_mov;
+}
+
+hipError_t launch_batch_step(int storage, const BatchLaunch &L);
 hipError_t launch_classify(const Box &bx, uint8_t *own, hipStream_t s);
 hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int side, uint8_t *own, int check,
                              int *err, hipStream_t s);

@@ -28,8 +28,11 @@ EXPORTED = [
     "lb_read_fields", "lb_force_torque", "lb_force_parts", "lb_body_state", "lb_links",
     "lb_read_populations", "lb_write_populations", "lb_audit", "lb_info", "lb_state_size",
     "lb_save_state", "lb_load_state", "lb_kernel_timing", "lb_kernel_time", "lb_destroy",
-    "lb_strerror",
+    "lb_strerror", "lb_server_create", "lb_server_submit", "lb_server_progress", "lb_server_results",
+    "lb_server_stats_get", "lb_server_clock", "lb_server_destroy",
 ]
+LB_REQ_MAXBODY = 8
+LB_SERVER_MAXACTIVE = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -49,6 +52,34 @@ class LbSquirmer(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("e", C.c_double * 3), ("R", C.c_double),
                 ("B1", C.c_double), ("beta", C.c_double), ("mode", C.c_int),
                 ("v", C.c_double * 3), ("w", C.c_double * 3), ("rho_p", C.c_double)]
+
+
+class LbServerParams(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("max_active", C.c_int), ("chunk_steps", C.c_int),
+                ("use_graph", C.c_int), ("storage", C.c_int), ("scale_log2", C.c_int),
+                ("wca_sigma", C.c_double), ("wca_eps", C.c_double), ("stream", C.c_void_p)]
+
+
+class LbRequest(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("nu", C.c_double),
+                ("nbody", C.c_int), ("body", LbSquirmer * LB_REQ_MAXBODY), ("nsteps", C.c_int64),
+                ("tag", C.c_uint64)]
+
+
+_V3 = (C.c_double * 3) * LB_REQ_MAXBODY
+
+
+class LbResult(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int), ("nbody", C.c_int),
+                ("steps", C.c_int64), ("fluid_cells", C.c_uint64),
+                ("pos", _V3), ("e", _V3), ("v", _V3), ("w", _V3), ("F", _V3), ("T", _V3),
+                ("mass", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class LbServerStats(C.Structure):
+    _fields_ = [("cell_updates", C.c_uint64), ("chunks", C.c_uint64), ("graphs", C.c_uint64),
+                ("completed", C.c_uint64), ("arena_in_use", C.c_size_t)]
 
 
 class LBError(RuntimeError):
@@ -92,6 +123,13 @@ def load():
         "lb_kernel_timing": [vp, ip],
         "lb_kernel_time": [vp, dp, C.POINTER(C.c_int64)],
         "lb_destroy": [vp],
+        "lb_server_create": [C.POINTER(LbServerParams), C.POINTER(vp)],
+        "lb_server_submit": [vp, C.POINTER(LbRequest), C.POINTER(C.c_uint64)],
+        "lb_server_progress": [vp, ip, C.POINTER(ip), C.POINTER(ip)],
+        "lb_server_results": [vp, C.POINTER(LbResult), ip, C.POINTER(ip)],
+        "lb_server_stats_get": [vp, C.POINTER(LbServerStats)],
+        "lb_server_clock": [vp, dp],
+        "lb_server_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -145,6 +183,19 @@ def _torch_cuda():
         return torch if torch.cuda.is_available() else None
     except Exception:
         return None
+
+
+def _squirmer(pos, e=(1.0, 0.0, 0.0), R=4.0, B1=0.0, beta=0.0, mode="free", v=(0.0, 0.0, 0.0),
+              w=(0.0, 0.0, 0.0), rho_p=0.0, out=None):
+    q = out if out is not None else LbSquirmer()
+    q.pos = (C.c_double * 3)(*map(float, pos))
+    q.e = (C.c_double * 3)(*map(float, e))
+    q.R, q.B1, q.beta = float(R), float(B1), float(beta)
+    q.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    q.v = (C.c_double * 3)(*map(float, v))
+    q.w = (C.c_double * 3)(*map(float, w))
+    q.rho_p = float(rho_p)
+    return q
 
 
 class Sim:
@@ -207,14 +258,7 @@ class Sim:
 
     def add_squirmer(self, pos, e=(1.0, 0.0, 0.0), R=4.0, B1=0.0, beta=0.0, mode="free",
                      v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), rho_p=0.0):
-        q = LbSquirmer()
-        q.pos = (C.c_double * 3)(*map(float, pos))
-        q.e = (C.c_double * 3)(*map(float, e))
-        q.R, q.B1, q.beta = float(R), float(B1), float(beta)
-        q.mode = MODES[mode] if isinstance(mode, str) else int(mode)
-        q.v = (C.c_double * 3)(*map(float, v))
-        q.w = (C.c_double * 3)(*map(float, w))
-        q.rho_p = float(rho_p)
+        q = _squirmer(pos, e, R, B1, beta, mode, v, w, rho_p)
         i = C.c_int(-1)
         _check(load().lb_add_squirmer(self.h, C.byref(q), C.byref(i)), "lb_add_squirmer")
         self.nbody += 1
@@ -313,3 +357,89 @@ class Sim:
 def step_batch(sims, nsteps):
     arr = (C.c_void_p * len(sims))(*[s.h for s in sims])
     _check(load().lb_step_batch(arr, len(sims), int(nsteps)), "lb_step_batch")
+
+
+class Server:
+    """Continuous-batching server of independent squirmer simulations
+    (``lb_server_*``): requests are queued, admitted by device-memory budget,
+    advanced together in batched chunks and retired with their results."""
+
+    def __init__(self, budget_bytes, max_active=16, chunk_steps=100, use_graph=True, storage="f32",
+                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, stream=None):
+        L = load()
+        p = LbServerParams()
+        p.budget_bytes = int(budget_bytes)
+        p.max_active = int(max_active)
+        p.chunk_steps = int(chunk_steps)
+        p.use_graph = 1 if use_graph else 0
+        p.storage = STORAGE[storage]
+        p.scale_log2 = int(14 if (scale_log2 is None and storage == "f16") else (scale_log2 or 0))
+        p.wca_sigma, p.wca_eps = float(wca_sigma), float(wca_eps)
+        p.stream = stream
+        h = C.c_void_p()
+        _check(L.lb_server_create(C.byref(p), C.byref(h)), "lb_server_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, shape, bodies, nsteps, nu=1.0 / 6.0, tag=0):
+        """Queue one request; bodies is a list of keyword dicts of
+        ``Sim.add_squirmer``.  Returns the ticket."""
+        if len(bodies) > LB_REQ_MAXBODY:
+            raise ValueError("at most %d bodies per request" % LB_REQ_MAXBODY)
+        rq = LbRequest()
+        rq.nx, rq.ny, rq.nz = (int(v) for v in shape)
+        rq.nu = float(nu)
+        rq.nbody = len(bodies)
+        for i, b in enumerate(bodies):
+            _squirmer(out=rq.body[i], **b)
+        rq.nsteps = int(nsteps)
+        rq.tag = int(tag)
+        t = C.c_uint64()
+        _check(load().lb_server_submit(self.h, C.byref(rq), C.byref(t)), "lb_server_submit")
+        return t.value
+
+    def progress(self, wait=False):
+        a, q = C.c_int(), C.c_int()
+        _check(load().lb_server_progress(self.h, 1 if wait else 0, C.byref(a), C.byref(q)),
+               "lb_server_progress")
+        return a.value, q.value
+
+    def results(self, cap=256):
+        buf = (LbResult * cap)()
+        n = C.c_int()
+        _check(load().lb_server_results(self.h, buf, cap, C.byref(n)), "lb_server_results")
+        out = []
+        for r in buf[:n.value]:
+            nb = r.nbody
+            d = {k: getattr(r, k) for k in ("ticket", "tag", "status", "nbody", "steps", "fluid_cells",
+                                             "mass", "t_submit", "t_admit", "t_done")}
+            for k in ("pos", "e", "v", "w", "F", "T"):
+                d[k] = np.array([list(getattr(r, k)[i]) for i in range(nb)]).reshape(nb, 3)
+            out.append(d)
+        return out
+
+    def stats(self):
+        st = LbServerStats()
+        _check(load().lb_server_stats_get(self.h, C.byref(st)), "lb_server_stats_get")
+        return {k: getattr(st, k) for k, _ in LbServerStats._fields_}
+
+    def clock(self):
+        t = C.c_double()
+        _check(load().lb_server_clock(self.h, C.byref(t)), "lb_server_clock")
+        return t.value

@@ -67,3 +67,47 @@ def test_null_arguments_rejected():
     assert L.lb_destroy(None) == lbsq.LB_EINVAL
     assert L.lb_step_batch(None, -1, 1) == lbsq.LB_EINVAL
     assert L.lb_audit(None, None, None) == lbsq.LB_EINVAL
+
+
+def _server_params(**kw):
+    p = lbsq.LbServerParams()
+    p.budget_bytes = 1 << 30
+    p.max_active, p.chunk_steps, p.use_graph = 4, 10, 1
+    p.storage, p.scale_log2 = 0, 0
+    p.wca_sigma, p.wca_eps = 1.0, 0.01
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [
+    dict(budget_bytes=1000), dict(max_active=0), dict(max_active=65), dict(chunk_steps=0),
+    dict(chunk_steps=100001), dict(storage=5), dict(scale_log2=-2), dict(wca_sigma=0.0),
+    dict(wca_eps=-0.5),
+])
+def test_server_create_rejects_bad_parameters(kw):
+    """Checked before any device call, so this runs without a GPU."""
+    L = lbsq.load()
+    h = C.c_void_p(77)
+    assert L.lb_server_create(C.byref(_server_params(**kw)), C.byref(h)) == lbsq.LB_EINVAL
+    assert h.value is None
+
+
+def test_server_null_arguments_rejected():
+    L = lbsq.load()
+    n = C.c_int()
+    assert L.lb_server_create(None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_submit(None, None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_progress(None, 0, None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_results(None, None, 0, C.byref(n)) == lbsq.LB_EINVAL
+    assert L.lb_server_stats_get(None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_clock(None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_destroy(None) == lbsq.LB_EINVAL
+
+
+def test_request_layout_matches_header():
+    """The binding's request and result records have the C layout the
+    header implies (8-byte aligned members, 8 bodies)."""
+    assert C.sizeof(lbsq.LbSquirmer) == 8 * (3 + 3 + 3 + 1 + 3 + 3 + 1)
+    assert C.sizeof(lbsq.LbRequest) == 4 * 3 + 4 + 8 + 8 + 8 * C.sizeof(lbsq.LbSquirmer) + 8 + 8
+    assert C.sizeof(lbsq.LbResult) == 8 * 2 + 4 * 2 + 8 * 2 + 6 * 8 * 3 * 8 + 8 * 4
