@@ -6,9 +6,11 @@ deviation storage.  One step is the whole path: geometry, conversion, force
 and torque, fused stream-collide-bounce-back, rigid-body update.
 
 Prints one JSON line: MLUPS over fluid cells (inputs resident in HBM), the
-roofline of the fused stream-collide kernel measured with HIP events on the
-stream it runs on, the same figures for FP16 deviation storage, and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+roofline of the fluid-update kernel measured with HIP events on the stream it
+runs on, the same figures for FP16 deviation storage, the served form (a
+seeded Poisson stream of independent requests through the continuous-batching
+server: capacity, then p50/p99 latency at a fixed rate, FP32 and FP16), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -61,6 +63,80 @@ def run_gpu(storage, shape, R, beta, steps, warmup):
     }
 
 
+def serve(storage, reqs, arrivals, chunk, max_active, budget):
+    """Run the request stream through a server; arrivals None = all at once.
+    Latency of a request = completion time - scheduled arrival."""
+    import numpy as np
+    from paper_1903_04799_amd import lbsq
+    n = len(reqs)
+    order = list(range(n))
+    if arrivals is None:
+        arrivals = np.zeros(n)
+    done = {}
+    with lbsq.Server(budget, max_active=max_active, chunk_steps=chunk, use_graph=True, storage=storage) as sv:
+        t0 = sv.clock()
+        nxt = 0
+        while len(done) < n:
+            now = sv.clock() - t0
+            while nxt < n and arrivals[order[nxt]] <= now:
+                j = order[nxt]
+                shape, bodies, steps = reqs[j]
+                sv.submit(shape, bodies, steps, tag=j)
+                nxt += 1
+            active, queued = sv.progress()
+            for r in sv.results():
+                done[r["tag"]] = r
+            if len(done) == n:
+                break
+            if active == 0 and queued == 0 and nxt < n:
+                time.sleep(max(0.0, min(0.05, arrivals[order[nxt]] - (sv.clock() - t0))))
+            elif active or queued:
+                sv.progress(wait=True)
+                for r in sv.results():
+                    done[r["tag"]] = r
+        stats = sv.stats()
+    bad = [r for r in done.values() if r["status"] != 0]
+    if bad:
+        raise RuntimeError("served request failed: %s" % lbsq.strerror(bad[0]["status"]))
+    lat = np.array([done[j]["t_done"] - t0 - arrivals[j] for j in range(n)])
+    t_end = max(r["t_done"] for r in done.values()) - t0
+    span = t_end - float(np.min(arrivals))
+    # swim speed along e of each single squirmer after its run, per request
+    speed = {j: float(np.dot(done[j]["v"][0], done[j]["e"][0])) for j in range(n) if done[j]["nbody"] == 1}
+    return {"mlups": stats["cell_updates"] / span / 1e6, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+            "p99_ms": float(np.percentile(lat, 99)) * 1e3, "span_s": span, "req_per_s": n / span,
+            "chunks": stats["chunks"], "graphs": stats["graphs"], "speed": speed}
+
+
+def run_served(n_req, seed, chunk, max_active, budget_gb, storages):
+    """Capacity (all requests at once) in FP32, then each storage at a fixed
+    Poisson rate of 0.6 x that capacity."""
+    import numpy as np
+    from paper_1903_04799_amd import workloads
+    budget = int(budget_gb * (1 << 30))
+    reqs = workloads.request_stream(n_req, seed=seed)
+    warm = workloads.request_stream(2, seed=seed + 1, steps=50)
+    serve("f32", warm, None, chunk, max_active, budget)
+    cap = serve("f32", reqs, None, chunk, max_active, budget)
+    qps = 0.6 * cap["req_per_s"]
+    arrivals = workloads.poisson_arrivals(n_req, qps, seed=seed)
+    out = {"workload": "Poisson stream of %d requests (seed %d): cubic boxes {48..192}^3, R {4,6,8,12}, "
+                       "beta U[-5,5], B1 1e-3, 1000 steps, half single squirmers, half pairs" % (n_req, seed),
+           "capacity_req_per_s": round(cap["req_per_s"], 2), "capacity_mlups": round(cap["mlups"], 1),
+           "qps": round(qps, 2), "chunk_steps": chunk, "max_active": max_active}
+    speeds = {}
+    for st in storages:
+        r = serve(st, reqs, arrivals, chunk, max_active, budget)
+        speeds[st] = r.pop("speed")
+        out[st] = {"mlups": round(r["mlups"], 1), "p50_ms": round(r["p50_ms"], 1), "p99_ms": round(r["p99_ms"], 1),
+                   "req_per_s": round(r["req_per_s"], 2), "chunks": r["chunks"], "graphs": r["graphs"]}
+    if "f32" in speeds and "f16" in speeds:
+        rel = [abs(speeds["f16"][j] - speeds["f32"][j]) / abs(speeds["f32"][j]) for j in speeds["f32"]
+               if speeds["f32"][j] != 0.0]
+        out["f16_swim_speed_rel_diff_max"] = float(np.max(rel)) if rel else None
+    return out
+
+
 def cpu_baseline(shape, R, beta, seconds):
     from oracle import oracle as O
     O.build()
@@ -91,6 +167,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,6 +213,9 @@ def main():
                                "kernel_us": round(f16["kernel_us"], 2),
                                "kernel_gbs": round(f16["kernel_gbs"], 1), "bytes_per_update": 76,
                                "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3)}
+    if not args.no_serve:
+        out["served"] = run_served(args.serve_requests, args.serve_seed, args.serve_chunk, args.serve_active,
+                                   args.serve_budget_gb, ["f32"] if args.no_fp16 else ["f32", "f16"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(shape, args.R, args.beta, args.cpu_seconds)
     print(json.dumps(out), flush=True)
