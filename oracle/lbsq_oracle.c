@@ -30,8 +30,12 @@
  *     the "magic" product Lambda = (1/lambda_e - 1/2)(1/lambda_o - 1/2);
  *   - the reflected population is the fluid node's own post-collision
  *     f_ibar(x_f) and rho in the wall term is the local density at x_f;
- *   - the wall velocity is evaluated at the solid node centre r_b and equals
- *     v + w x d + slip(d/|d|), d = minimum image of r_b - r;
+ *   - the wall velocity of a link is v + w x m + slip(m/|m|), evaluated at
+ *     the link midpoint m = r_b + c_i/2 - r (minimum image), where the
+ *     halfway bounce-back wall lies; the text names the boundary node r_b,
+ *     but only the midpoint reproduces the swim speeds the paper plots in
+ *     its resolution study (the solid node centre gives speeds 5-13% high,
+ *     the fluid node 5-15% low, at R = 4..12);
  *   - force: sum over boundary links only of -c_i (f_ibar*(x) + f_i^in(x));
  *     torque with lever arm d to the solid node centre;
  *   - conversion: "+" for cells the body covers, "-" for cells it uncovers,
@@ -426,8 +430,12 @@ static double cell_rho(const or_sim *s, const double *f, size_t idx)
     return r;
 }
 
-/* Velocity of the solid node centred at cell (sx,sy,sz) with owner o. */
-static void boundary_velocity(const or_sim *s, uint8_t o, size_t sidx, int sx, int sy, int sz,
+/* Wall velocity of the link in direction i whose source, the solid node
+ * centred at cell (sx,sy,sz), has owner o.  For a body: eq. (vb) plus the
+ * slip of eq. (squirmer), evaluated where the halfway bounce-back wall of the
+ * link lies, at the link midpoint r_b + c_i/2; d receives the lever arm
+ * r_b - r of eq. (bbtorque). */
+static void boundary_velocity(const or_sim *s, uint8_t o, size_t sidx, int sx, int sy, int sz, int i,
                               double vb[3], double d[3])
 {
     d[0] = d[1] = d[2] = 0.0;
@@ -437,10 +445,11 @@ static void boundary_velocity(const or_sim *s, uint8_t o, size_t sidx, int sx, i
     }
     const or_body *b = &s->body[o - 1];
     lever(s, b, sx, sy, sz, d);
-    double wxd[3], slip[3] = {0.0, 0.0, 0.0};
-    cross(b->w, d, wxd);
-    if (b->B1 != 0.0) or_slip(d, b->e, b->B1, b->beta, slip);
-    for (int k = 0; k < 3; ++k) vb[k] = b->v[k] + wxd[k] + slip[k];
+    double m[3] = {d[0] + 0.5 * CX[i], d[1] + 0.5 * CY[i], d[2] + 0.5 * CZ[i]};
+    double wxm[3], slip[3] = {0.0, 0.0, 0.0};
+    cross(b->w, m, wxm);
+    if (b->B1 != 0.0) or_slip(m, b->e, b->B1, b->beta, slip);
+    for (int k = 0; k < 3; ++k) vb[k] = b->v[k] + wxm[k] + slip[k];
 }
 
 /* Incoming population i at fluid cell x after streaming with bounce-back.
@@ -456,7 +465,7 @@ static double incoming(const or_sim *s, const double *f, size_t idx, int x, int 
         return f[i * s->n + sidx];
     }
     *is_link = 1;
-    boundary_velocity(s, o, sidx, sx, sy, sz, vb, d);
+    boundary_velocity(s, o, sidx, sx, sy, sz, i, vb, d);
     double rw = cell_rho(s, f, idx);
     *rho_w = rw;
     double cv = CX[i] * vb[0] + CY[i] * vb[1] + CZ[i] * vb[2];

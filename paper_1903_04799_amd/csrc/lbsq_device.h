@@ -2,8 +2,8 @@
 // lattice Boltzmann squirmer library (arXiv:1903.04799).
 //
 // Lattice, storage formats, the body table and the small device functions
-// that more than one kernel must evaluate identically (inside test, wall
-// velocity, bounce-back shift, refill density).
+// that more than one kernel must evaluate identically (inside test, box
+// geometry, lever arms).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -232,33 +232,6 @@ __device__ __forceinline__ bool in_bbox(const Box &b, const BT &B, int x, int y,
     bbox_origin(B, o, g);
     const int side = 2 * (B.H + g) + 1;
     return wrap(x - o[0], b.nx) < side && wrap(y - o[1], b.ny) < side && wrap(z - o[2], b.nz) < side;
-}
-
-// Wall velocity of the solid node of body B centred at cell s, eq. (vb) plus
-// the slip of eq. (squirmer): v + w x d + B1 (1 + beta e.n)((e.n) n - e).
-__device__ __forceinline__ void wall_velocity(const DevBody &B, const double d[3], double vb[3])
-{
-    vb[0] = B.v[0] + B.w[1] * d[2] - B.w[2] * d[1];
-    vb[1] = B.v[1] + B.w[2] * d[0] - B.w[0] * d[2];
-    vb[2] = B.v[2] + B.w[0] * d[1] - B.w[1] * d[0];
-    if (B.B1 != 0.0) {
-        const double ir = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double n[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-        const double en = B.e[0] * n[0] + B.e[1] * n[1] + B.e[2] * n[2];
-        const double a = B.B1 * (1.0 + B.beta * en);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) vb[k] += a * (en * n[k] - B.e[k]);
-    }
-}
-
-// Shift of the reflected population for the link (x, i) whose source node s
-// = x - c_i belongs to body B: 6 w_i rho_w c_i.v_b (moving-wall rule).
-__device__ __forceinline__ float bounce_shift(int i, float rho_w, const DevBody &B, const double d[3])
-{
-    double vb[3];
-    wall_velocity(B, d, vb);
-    const double cv = rcx(i) * vb[0] + rcy(i) * vb[1] + rcz(i) * vb[2];
-    return static_cast<float>(6.0 * wgt(i) * static_cast<double>(rho_w) * cv);
 }
 
 }  // namespace lbsq

@@ -442,10 +442,12 @@ __device__ __forceinline__ bool first_box(const Box &bx, const BT *bodies, const
 
 // The link of cell (x, y, z) in direction i whose source s = x - c_i is a
 // cell of body B: returns f_i^in = f_ibar*(x) + 6 w_i rho_w c_i.v_b, with the
-// wall velocity eq. (vb) plus the slip of eq. (squirmer) at the centre of s.
+// wall velocity eq. (vb) plus the slip of eq. (squirmer) taken at the link
+// midpoint (centre of s + c_i/2), where the halfway bounce-back wall lies.
 // The momentum handed to the body, -c_i (f_ibar*(x) + f_i^in(x)), is split
-// into its small part (FP32 force and torque in fv) and the pressure part
-// -c_i 2 w_i rho0 (integer counts kf, kr).
+// into its small part (FP32 force and torque in fv, lever arm to the centre
+// of s as in eq. (bbtorque)) and the pressure part -c_i 2 w_i rho0 (integer
+// counts kf, kr).
 __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int i, int x, int y, int z, float fob,
                                            float rho_w, float (&fv)[6], int (&kf)[3], int (&kr)[3])
 {
@@ -454,17 +456,18 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
     const int sc[3] = {x - c[0], y - c[1], z - c[2]};
     const int n[3] = {bx.nx, bx.ny, bx.nz};
     int r[3];
-    float d[3];
+    float d[3], m[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         r[a] = wrap_small(sc[a] - (B.ip[a] - B.H), n[a]) - B.H;  // source relative to floor(pos)
         d[a] = (float(r[a]) + 0.5f) - B.fr[a];
+        m[a] = d[a] + 0.5f * float(c[a]);
     }
-    float vb[3] = {B.v[0] + B.w[1] * d[2] - B.w[2] * d[1], B.v[1] + B.w[2] * d[0] - B.w[0] * d[2],
-                   B.v[2] + B.w[0] * d[1] - B.w[1] * d[0]};
+    float vb[3] = {B.v[0] + B.w[1] * m[2] - B.w[2] * m[1], B.v[1] + B.w[2] * m[0] - B.w[0] * m[2],
+                   B.v[2] + B.w[0] * m[1] - B.w[1] * m[0]};
     if (B.B1 != 0.0f) {
-        const float ir = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const float nn[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+        const float ir = rsqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        const float nn[3] = {m[0] * ir, m[1] * ir, m[2] * ir};
         const float en = B.e[0] * nn[0] + B.e[1] * nn[1] + B.e[2] * nn[2];
         const float am = B.B1 * (1.0f + B.beta * en);
 #pragma unroll

@@ -465,3 +465,41 @@ def test_rates_follow_viscosity_and_magic():
     # nu = (1/lam_e - 1/2)/3 and (1/lam_e - 1/2)(1/lam_o - 1/2) = Lambda
     assert abs((1 / le - 0.5) / 3 - 1 / 6) < 1e-15
     assert abs((1 / le - 0.5) * (1 / lo - 0.5) - 3 / 16) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# P11 (oracle part): the free squirmer's swim speed against the speeds the
+# paper plots for the same method in its resolution study (fixture with
+# citation under tests/golden).  This pins the evaluation point of the wall
+# velocity: at the link midpoint the oracle lands within a few per cent of
+# the paper; at the solid node centre it swims 13% fast, at the fluid node
+# 13% slow (R = 4).
+GOLDEN = __import__("pathlib").Path(__file__).resolve().parent / "golden" / "fig_resolution_swim_speed.txt"
+
+
+def paper_swim_speed(R, L_over_R):
+    for line in GOLDEN.read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            r, l, v = line.split()
+            if int(r) == R and int(l) == L_over_R:
+                return float(v)
+    raise KeyError((R, L_over_R))
+
+
+@pytest.mark.slow
+def test_P11_swim_speed_matches_paper_R4():
+    R, L, B1 = 4.0, 40, 1e-3
+    v0 = 2.0 * B1 / 3.0  # eq. (squirmer-speed)
+    o = O.OracleSim(L, L, L)
+    o.add_body((L / 2, L / 2, L / 2), (1.0, 0.0, 0.0), R, B1=B1, beta=0.0)
+    speeds = []
+    for t in range(1000):
+        o.step(1)
+        b = o.body(0)
+        speeds.append(float(np.dot(b["v"], b["e"])) / v0)
+    mean = float(np.mean(speeds[300:]))
+    ref = paper_swim_speed(4, 10)
+    # the paper's own series at R = 4 differ by 0.9% between box sizes and
+    # the instantaneous speed fluctuates by about 1%: 3% separates the
+    # readings by a factor of four
+    assert abs(mean / ref - 1.0) < 0.03, (mean, ref)
