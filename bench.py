@@ -15,16 +15,60 @@ the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+from pathlib import Path
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 152, "f16": 76, "bf16": 76}
+
+
+TRAFFIC_FILE = Path(ROOT) / "profiles" / "k_fluid_128cube_traffic.md"
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for f in ("lbsq_kernels.hip", "lbsq_device.h", "lbsq_launch.h"):
+        h.update((Path(ROOT) / "paper_1903_04799_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, shape, R):
+    """HBM bytes per launch of the fluid kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size); None
+    unless the kernels are the ones the counters were taken on and the
+    workload is the one they were taken for."""
+    if tuple(shape) != (128, 128, 128) or R != 8.0 or not TRAFFIC_FILE.exists():
+        return None
+    kv = {}
+    for line in TRAFFIC_FILE.read_text().splitlines():
+        if "=" in line and not line.startswith(("#", " ", "|")):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("traffic_sources_sha256_16") != kernel_sources_hash():
+        return None
+    v = kv.get("traffic_bytes_per_launch_" + storage)
+    return float(v) if v else None
+
+
+def copy_calibration(mib, reps=5):
+    """A plain device-to-device copy of known size (torch's copy kernel), run
+    beside the step so that hardware byte counters (FETCH_SIZE, WRITE_SIZE)
+    can be scaled by what they read for exactly mib MiB in and out."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def run_gpu(storage, shape, R, beta, steps, warmup):
@@ -168,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-seed", type=int, default=0)
     ap.add_argument("--serve-chunk", type=int, default=100)
@@ -184,6 +230,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     shape = (args.n, args.n, args.n)
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
     f32 = run_gpu("f32", shape, args.R, args.beta, args.steps, args.warmup)
     out = {
         "metric": "D3Q19 MLUPS FP32 vs FP16-storage; served sweep p50/p99 latency at fixed error",
@@ -202,7 +250,9 @@ def main():
                    "R": args.R, "beta": args.beta, "B1": 1e-3, "nu": 1 / 6, "storage": "f32 deviations",
                    "n_fluid": f32["n_fluid"]},
         "roofline": {"bound": "hbm", "achieved": round(f32["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(f32["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(f32["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("f32", shape, args.R), "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes_per_launch": f32["bytes_per_launch"],
                      "kernel": "k_fluid", "kernel_us": round(f32["kernel_us"], 2),
                      "bytes_per_update": BYTES_PER_UPDATE["f32"]},
     }
@@ -212,6 +262,7 @@ def main():
                                "ms_per_step": round(f16["ms_per_step"], 5),
                                "kernel_us": round(f16["kernel_us"], 2),
                                "kernel_gbs": round(f16["kernel_gbs"], 1), "bytes_per_update": 76,
+                               "traffic": measured_traffic("f16", shape, args.R),
                                "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3)}
     if not args.no_serve:
         out["served"] = run_served(args.serve_requests, args.serve_seed, args.serve_chunk, args.serve_active,
