@@ -377,3 +377,76 @@ def test_full_size_box_128_few_steps():
     err, _ = rel_u_err(s, o)
     assert err <= U_TOL, err
     check_bodies(s, o, [body])
+
+
+@pytest.mark.slow
+def test_full_size_tube_96x96x512():
+    """The confined scene at its real size: 96 x 96 x 512 box, static tube
+    wall of radius 24 about the z axis (80% of the cells are wall), squirmer
+    R = 12 on the axis swimming along +z (a puller, beta = 3); a few steps
+    field by field and the boundary-link set bit for bit."""
+    note("tube 96x96x512 R=12 beta=3, 3 steps")
+    shape = (96, 96, 512)
+    mask = scenes.tube_mask(*shape, 24.0)
+    body = dict(pos=(48.0, 48.0, 256.0), e=(0, 0, 1), R=12.0, B1=1e-3, beta=3.0)
+    o, s = make_pair(shape, [body], mask=mask)
+    o.step(3)
+    s.step(3)
+    err, drho = rel_u_err(s, o)
+    note("  u rel err %.2e, rho err %.2e" % (err, drho))
+    assert err <= U_TOL, err
+    check_bodies(s, o, [body])
+    cell, d, own = s.links()
+    oc, od, oo = o.links()
+    assert np.array_equal(cell, oc) and np.array_equal(d, od) and np.array_equal(own, oo)
+
+
+@pytest.mark.slow
+def test_full_size_obstacle_256():
+    """The near-field scene at its real size: 256^3 box, fixed no-slip sphere
+    A = 32 at the centre, squirmer R = 16 (a pusher, beta = -3) approaching it
+    at an impact parameter drawn from the seed; one step field by field."""
+    sc = scenes.obstacle_scene(0)
+    note("obstacle 256^3 A=32, squirmer R=16 at b=%.3f, 1 step" % sc["b"])
+    bodies = [dict(pos=sc["obstacle"], R=sc["A"], mode="fixed"),
+              dict(pos=sc["squirmer"], e=(1, 0, 0), R=sc["R"], B1=1e-3, beta=-3.0)]
+    o, s = make_pair((256, 256, 256), bodies)
+    o.step(1)
+    s.step(1)
+    err, drho = rel_u_err(s, o)
+    note("  u rel err %.2e, rho err %.2e" % (err, drho))
+    assert err <= U_TOL, err
+    check_bodies(s, o, bodies[1:])
+
+
+@pytest.mark.slow
+def test_reduced_precision_tube():
+    """The precision form on the tube scene: FP16 (scale 2^14) and BF16
+    deviation storage, FP32 collision, FP64 forces and integration, against
+    the FP64 oracle after 20 steps: velocity-field L2 error (FP16 <= 1e-3,
+    BF16 <= 2e-2) and the swimmer's velocity (0.5%, 5%)."""
+    lbsq = gpu()
+    note("tube 96x96x512, FP16 and BF16 storage, 20 steps")
+    shape = (96, 96, 512)
+    mask = scenes.tube_mask(*shape, 24.0)
+    body = dict(pos=(48.0, 48.0, 256.0), e=(0, 0, 1), R=12.0, B1=1e-3, beta=0.0)
+    o = O.OracleSim(*shape)
+    o.set_static_mask(mask)
+    o.add_body(body["pos"], body["e"], body["R"], B1=body["B1"], beta=body["beta"])
+    o.step(20)
+    _, u_o, own_o = o.fields()
+    fl = own_o == 0
+    vo = o.body(0)["v"][2]
+    for storage, l2_tol, v_tol in (("f16", 1e-3, 5e-3), ("bf16", 2e-2, 5e-2)):
+        s = lbsq.Sim(shape, storage=storage)
+        s.set_static_mask(mask)
+        s.add_squirmer(body["pos"], body["e"], body["R"], B1=body["B1"], beta=body["beta"])
+        s.step(20)
+        _, u, own = s.fields()
+        assert np.array_equal(own, own_o)
+        l2 = np.linalg.norm((u - u_o)[:, fl]) / np.linalg.norm(u_o[:, fl])
+        vg = s.body(0)["v"][2]
+        s.close()
+        note("  %s L2 %.2e, swim velocity %.6e vs %.6e" % (storage, l2, vg, vo))
+        assert l2 <= l2_tol
+        assert abs(vg - vo) <= v_tol * abs(vo)
