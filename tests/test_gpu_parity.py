@@ -450,3 +450,29 @@ def test_reduced_precision_tube():
         note("  %s L2 %.2e, swim velocity %.6e vs %.6e" % (storage, l2, vg, vo))
         assert l2 <= l2_tol
         assert abs(vg - vo) <= v_tol * abs(vo)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_storage_rounds_to_nearest_even(storage):
+    """Populations written through the ABI are stored as deviations
+    f - w_i rho0, scaled by 2^14 (FP16) or 1 (BF16), rounded to nearest even;
+    reading them back must give exactly that rounding (numpy's float16 cast
+    is round-to-nearest-even; BF16 is rounded here on the float32 bits)."""
+    lbsq = gpu()
+    shape = (16, 12, 10)
+    _, w = O.lattice()
+    rng = np.random.default_rng(11)
+    dev = rng.uniform(-2e-3, 2e-3, size=(19,) + shape[::-1]) * 10.0 ** rng.integers(-3, 1, size=(19,) + shape[::-1])
+    f = w[:, None, None, None] + dev
+    s = lbsq.Sim(shape, storage=storage)
+    s.set_populations(f)
+    got = s.populations()
+    d32 = (f - w[:, None, None, None]).astype(np.float32)
+    if storage == "f16":
+        q = (d32 * np.float32(2.0 ** 14)).astype(np.float16).astype(np.float64) / 2.0 ** 14
+    else:
+        u = d32.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+        q = (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    want = w[:, None, None, None] + q
+    assert np.array_equal(got, want), np.abs(got - want).max()
