@@ -115,8 +115,9 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
 {
     std::memset(&d, 0, sizeof(d));
     d.a = s->args;
+    d.f = s->f;
     for (int k = 0; k < 2; ++k) {
-        d.f[k] = s->f[k];
+        d.dens[k] = s->d_dens[k];
         d.own[k] = s->own[k];
         d.bodies[k] = s->d_bodies[k];
     }
@@ -173,12 +174,25 @@ int mirror_owner(lb_sim *s)
     return LB_OK;
 }
 
+// whether the last completed step had an even index (the in-place layout)
+bool after_even(const lb_sim *s) { return (s->steps & 1) == 1; }
+
+// Link densities of the cells next to a body, for the next step.
+int refresh_dens(lb_sim *s)
+{
+    return launch_dens(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), s->d_dens[(s->steps + 1) & 1],
+                       s->stream) == hipSuccess
+               ? LB_OK
+               : LB_EDEVICE;
+}
+
 int classify_now(lb_sim *s)
 {
     if (!s->need_classify) return LB_OK;
     if (launch_classify(s->args.box, s->own[s->cur], s->stream) != hipSuccess) return LB_EDEVICE;
     s->need_classify = false;
-    return mirror_owner(s);
+    const int rc = mirror_owner(s);
+    return rc == LB_OK ? refresh_dens(s) : rc;
 }
 
 }  // namespace
@@ -222,8 +236,9 @@ int lb_destroy(lb_sim *s)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    dev_free(s, s->f);
     for (int k = 0; k < 2; ++k) {
-        dev_free(s, s->f[k]);
+        dev_free(s, s->d_dens[k]);
         dev_free(s, s->own[k]);
         dev_free(s, s->d_bodies[k]);
     }
@@ -275,8 +290,9 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->esize = p->storage == LB_STORAGE_F32 ? 4 : 2;
 
     const size_t fbytes = size_t(Q) * bx.stride * s->esize;
+    s->f = dev_alloc(s, fbytes);
     for (int k = 0; k < 2; ++k) {
-        s->f[k] = dev_alloc(s, fbytes);
+        s->d_dens[k] = static_cast<float *>(dev_alloc(s, size_t(n) * sizeof(float)));
         s->own[k] = static_cast<uint8_t *>(dev_alloc(s, n));
         s->d_bodies[k] = static_cast<DevBody *>(dev_alloc(s, MAXB * sizeof(DevBody)));
     }
@@ -287,14 +303,14 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
     s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
     s->d_desc = static_cast<SimDesc *>(dev_alloc(s, sizeof(SimDesc)));
-    if (!s->f[0] || !s->f[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
+    if (!s->f || !s->d_dens[0] || !s->d_dens[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
         !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err || !s->d_desc) {
         lb_destroy(s);
         return LB_ENOMEM;
     }
-    hipError_t e = hipMemsetAsync(s->f[0], 0, fbytes, s->stream);
+    hipError_t e = hipMemsetAsync(s->f, 0, fbytes, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_acc, 0, NACCSET * ACCSET_SIZE * sizeof(unsigned long long), s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->f[1], 0, fbytes, s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(s->d_dens[k], 0, size_t(n) * sizeof(float), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->own[0], 0, n, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->own[1], 0, n, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, NERR * sizeof(int), s->stream);
@@ -432,7 +448,7 @@ int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
     uint8_t *d_o = static_cast<uint8_t *>(dev_alloc(s, n));
     int rc = LB_OK;
     if (!d_rho || !d_u || !d_o) rc = LB_ENOMEM;
-    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], d_rho, d_u, d_o, s->stream) !=
+    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), d_rho, d_u, d_o, s->stream) !=
                            hipSuccess)
         rc = LB_EDEVICE;
     if (rc == LB_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LB_EDEVICE;
@@ -549,7 +565,8 @@ int lb_read_populations(lb_sim *s, double *f)
     if (!buf) return LB_ENOMEM;
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
-        if (launch_plane(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], i, buf, 1, s->stream) != hipSuccess ||
+        if (launch_plane(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), i, buf, 1, s->stream) !=
+                hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess ||
             hipMemcpy(f + size_t(i) * n, buf, size_t(n) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             rc = LB_EDEVICE;
@@ -569,11 +586,13 @@ int lb_write_populations(lb_sim *s, const double *f)
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
         if (hipMemcpy(buf, f + size_t(i) * n, size_t(n) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            launch_plane(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], i, buf, 0, s->stream) != hipSuccess ||
+            launch_plane(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), i, buf, 0, s->stream) !=
+                hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess)
             rc = LB_EDEVICE;
     }
     dev_free(s, buf);
+    if (rc == LB_OK) rc = refresh_dens(s);
     return rc;
 }
 
@@ -581,8 +600,8 @@ static int audit_now(lb_sim *s, double out[5])
 {
     int st = sync_check(s);
     if (st != LB_OK) return st;
-    if (launch_audit(s->p.storage, s->args, s->f[s->cur], s->own[s->cur], s->d_audit_part, s->d_audit_out, s->d_err,
-                     s->stream) != hipSuccess)
+    if (launch_audit(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), s->d_audit_part, s->d_audit_out,
+                     s->d_err, s->stream) != hipSuccess)
         return LB_EDEVICE;
     st = sync_check(s);
     if (st != LB_OK) return st;
@@ -653,7 +672,7 @@ int lb_save_state(lb_sim *s, void *buf, size_t bytes)
     char *p = static_cast<char *>(buf);
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
-    if (hipMemcpy(p, s->f[s->cur], h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    if (hipMemcpy(p, s->f, h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
     if (hipMemcpy(p, s->own[s->cur], s->args.box.n, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += s->args.box.n;
@@ -678,7 +697,7 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     if (st != LB_OK) return st;
     const char *p = static_cast<const char *>(buf) + sizeof(h);
     s->cur = int(h.steps & 1);
-    if (hipMemcpy(s->f[s->cur], p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    if (hipMemcpy(s->f, p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
     for (int k = 0; k < 2; ++k)
         if (hipMemcpy(s->own[k], p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
@@ -698,6 +717,8 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     s->steps = h.steps;
     s->started = true;
     s->need_classify = false;
+    st = refresh_dens(s);
+    if (st != LB_OK) return st;
     return sync_check(s);
 }
 

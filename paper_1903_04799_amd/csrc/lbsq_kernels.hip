@@ -3,8 +3,9 @@
 //
 // A time step t is two launches on one stream, each covering every
 // simulation of a batch (one simulation is a batch of one):
-//   k_fluid           every fluid cell, A(t) -> B, FP32 arithmetic on stored
-//                     deviations, non-temporal stores.  Its leading blocks
+//   k_fluid           every fluid cell, in place on one population buffer
+//                     (the AA pattern described below), FP32 arithmetic on
+//                     stored deviations, non-temporal stores.  Its leading blocks
 //                     take the cells next to a body, found in the bodies'
 //                     boxes, one thread per (cell, direction): pull streaming
 //                     and the TRT collision of eq. (lb) with moving-wall
@@ -154,11 +155,9 @@ struct Nbr {
     }
 };
 
-// TRT collision of the incoming deviations f, stored to B[.][idx]; the audit
-// adds what was stored (as it will be read back).
-template <class S, bool AUDIT, bool FORCE>
-__device__ __forceinline__ void collide_store(const StepArgs &a, const float (&f)[Q], typename S::T *__restrict__ Bf,
-                                              uint32_t idx, double (&am)[5])
+// TRT collision of the incoming deviations f into out.
+template <bool FORCE>
+__device__ __forceinline__ void collide(const StepArgs &a, const float (&f)[Q], float (&out)[Q])
 {
     float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
@@ -178,7 +177,6 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&f
     const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
     const float usq = ux * ux + uy * uy + uz * uz;
     const float le = a.lam_e, lo = a.lam_o;
-    float out[Q];
     out[0] = f[0] - le * (f[0] - wgtf(0) * (drho - 1.5f * rho * usq));
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
@@ -205,29 +203,52 @@ __device__ __forceinline__ void collide_store(const StepArgs &a, const float (&f
             out[i + 1] += ce * se - co * so;
         }
     }
-    const uint64_t st = a.box.stride;
+}
+
+// The audit adds what is stored (as it will be read back).
+template <class S>
+__device__ __forceinline__ void audit_add(const StepArgs &a, const float (&out)[Q], double (&am)[5])
+{
 #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(S::st(out[i], a.scale), &Bf[i * st + idx]);
-    if (AUDIT) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double v = S::ld(S::st(out[i], a.scale), a.inv_scale);
-            am[0] += v;
-            am[1] += cx(i) * v;
-            am[2] += cy(i) * v;
-            am[3] += cz(i) * v;
-        }
-        am[4] = 1.0;
+    for (int i = 0; i < Q; ++i) {
+        const double v = S::ld(S::st(out[i], a.scale), a.inv_scale);
+        am[0] += v;
+        am[1] += cx(i) * v;
+        am[2] += cy(i) * v;
+        am[3] += cz(i) * v;
     }
+    am[4] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// In-place (AA) streaming on one population buffer F.  A step t reads the
+// incoming populations of every fluid cell and writes its post-collision
+// populations where the next step will read them:
+//   t even: f_i^in(x) = F[i][x];          f*_i(x) -> F[ibar][x]
+//   t odd:  f_i^in(x) = F[ibar][x - c_i];  f*_i(x) -> F[i][x + c_i]
+// so that between steps the post-collision population f*_j(x) sits in
+// F[jbar][x] after an even step and in F[j][x + c_j] after an odd one.  Every
+// slot is read and then written by the one cell that owns it in that step.
+// Bounce-back from a solid source s = x - c_i takes the cell's own f*_ibar(x),
+// which sits in F[ibar][s] before an even step and in F[i][x] before an odd
+// one; neither slot is written by anyone else in the step.
+
+// Slot of the post-collision population f*_j of cell (x, y, z) between steps,
+// after an even (after_even) or odd step.
+__device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y, int z, bool after_even)
+{
+    if (after_even) return uint64_t(opp(j)) * bx.stride + cell_of(bx, x, y, z);
+    return uint64_t(j) * bx.stride + cell_of(bx, wrap_small(x + rcx(j), bx.nx), wrap_small(y + rcy(j), bx.ny),
+                                             wrap_small(z + rcz(j), bx.nz));
 }
 
 // ---------------------------------------------------------------------------
 // the hot loop: every fluid cell without a body neighbour
 
-template <class S, bool AUDIT, bool FORCE>
-__device__ __forceinline__ void stream_collide_block(const StepArgs &a, const typename S::T *__restrict__ A,
-                                                     typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
-                                                     double *__restrict__ audit_part, uint32_t blk)
+template <class S, bool AUDIT, bool FORCE, bool ODD>
+__device__ __forceinline__ void stream_collide_block(const StepArgs &a, typename S::T *F,
+                                                     const uint8_t *__restrict__ own, double *__restrict__ audit_part,
+                                                     uint32_t blk)
 {
     const uint32_t idx = blk * BLOCK + threadIdx.x;
     const uint64_t st = a.box.stride;
@@ -238,17 +259,26 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, const ty
         float f[Q];
         if (o == OWN_FLUID) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = S::ld(A[i * st + nb.src(i)], a.inv_scale);
+            for (int i = 0; i < Q; ++i)
+                f[i] = S::ld(ODD ? F[opp(i) * st + nb.src(i)] : F[i * st + idx], a.inv_scale);
         } else {
             // no-slip walls: a population that would come from a wall is the
             // cell's own opposite post-collision population
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const uint32_t s = nb.src(i);
-                f[i] = is_fluid(own[s]) ? S::ld(A[i * st + s], a.inv_scale) : S::ld(A[opp(i) * st + idx], a.inv_scale);
+                const bool fl = is_fluid(own[s]);
+                const uint64_t at = ODD ? (fl ? opp(i) * st + s : i * st + idx) : (fl ? i * st + idx : opp(i) * st + s);
+                f[i] = S::ld(F[at], a.inv_scale);
             }
         }
-        collide_store<S, AUDIT, FORCE>(a, f, Bf, idx, am);
+        float out[Q];
+        collide<FORCE>(a, f, out);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            __builtin_nontemporal_store(S::st(out[i], a.scale),
+                                        &F[ODD ? i * st + nb.src(opp(i)) : opp(i) * st + idx]);
+        if (AUDIT) audit_add<S>(a, out, am);
     }
     if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
 }
@@ -497,18 +527,17 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
 // fluid, reflection at walls, moving-wall bounce-back at bodies, then the
 // collision.  Momentum exchange: integer sums, reduced over the block for
 // the box's own body.
-template <class S, bool AUDIT, bool FORCE>
-__device__ __forceinline__ void boundary_block(const StepArgs &a, const typename S::T *__restrict__ A,
-                                               typename S::T *__restrict__ Bf, const uint8_t *__restrict__ own,
+template <class S, bool AUDIT, bool FORCE, bool ODD>
+__device__ __forceinline__ void boundary_block(const StepArgs &a, typename S::T *F, const uint8_t *__restrict__ own,
                                                const DevBody *__restrict__ cur, int nbody,
                                                const int *__restrict__ ids, const int *__restrict__ start, int nlist,
                                                unsigned long long *__restrict__ acc,
+                                               const float *__restrict__ dens_prev, float *__restrict__ dens_cur,
                                                double *__restrict__ audit_part, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody LinkBody entries
     LinkBody *lb = reinterpret_cast<LinkBody *>(lds_dyn);
-    __shared__ float s_fo[CPB][Q + 1];
-    __shared__ float s_fin[CPB][Q + 1];
+    __shared__ float s_f[CPB][Q + 1];
     const Box &bx = a.box;
     const uint64_t st = bx.stride;
     const Slot sl = slot_of(bx, cur, ids, start, nlist, 0, blk);
@@ -517,20 +546,23 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, const typename
     const bool active = sl.valid && own[c] == OWN_NB_BODY && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 0);
     const uint32_t s = cell_of(bx, wrap_small(sl.x - rcx(i), bx.nx), wrap_small(sl.y - rcy(i), bx.ny),
                                wrap_small(sl.z - rcz(i), bx.nz));
-    float fa = 0.0f;
+    // one load per (cell, direction): the incoming population where the source
+    // is fluid, else the cell's own f*_ibar for the reflection
+    float fl = 0.0f;
     uint8_t os = OWN_FLUID;
     if (active) {
-        s_fo[sl.cl][i] = S::ld(A[i * st + c], a.inv_scale);
-        fa = S::ld(A[i * st + s], a.inv_scale);
         if (i > 0) os = own[s];
+        const bool from_fluid = is_fluid(os);
+        const uint64_t at = ODD ? (from_fluid ? opp(i) * st + s : i * st + c) : (from_fluid ? i * st + c : opp(i) * st + s);
+        fl = S::ld(F[at], a.inv_scale);
     }
     for (int b = threadIdx.x; b < nbody; b += BLOCK) {
         const DevBody &D = cur[b];
         LinkBody &L = lb[b];
         for (int k = 0; k < 3; ++k) {
-            const double fl = floor(D.pos[k]);
-            L.ip[k] = int(fl);
-            L.fr[k] = float(D.pos[k] - fl);
+            const double flo = floor(D.pos[k]);
+            L.ip[k] = int(flo);
+            L.fr[k] = float(D.pos[k] - flo);
             L.v[k] = float(D.v[k]);
             L.w[k] = float(D.w[k]);
             L.e[k] = float(D.e[k]);
@@ -543,36 +575,45 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, const typename
     int key = -1;  // body of this thread's link
     long long v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
-        float rw = 0.0f;
-#pragma unroll
-        for (int j = 0; j < Q; ++j) rw += s_fo[sl.cl][j];
-        rw += a.rho0;
-        const float fob = s_fo[sl.cl][i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1)];
-        float fin;
-        if (is_fluid(os)) {
-            fin = fa;
-        } else if (os == OWN_WALL) {
-            fin = fob;
-        } else {
+        float fin = fl;
+        if (is_body(os)) {
+            // local density of the cell's post-collision populations, kept
+            // from the previous step (its slots are rewritten in place)
+            const float rw = a.rho0 + dens_prev[c];
             key = os - 1;
             float fv[6];
             int kf[3], kr[3];
-            fin = body_link(bx, lb[key], i, sl.x, sl.y, sl.z, fob, rw, fv, kf, kr);
+            fin = body_link(bx, lb[key], i, sl.x, sl.y, sl.z, fl, rw, fv, kf, kr);
             for (int k = 0; k < 6; ++k) v[k] = to_fx(fv[k]);
             for (int k = 0; k < 3; ++k) {
                 v[6 + k] = kf[k];
                 v[9 + k] = kr[k];
             }
         }
-        s_fin[sl.cl][i] = fin;
+        s_f[sl.cl][i] = fin;
     }
     __syncthreads();
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && i == 0) {
-        float f[Q];
+        float f[Q], out[Q];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = s_fin[sl.cl][j];
-        collide_store<S, AUDIT, FORCE>(a, f, Bf, c, am);
+        for (int j = 0; j < Q; ++j) f[j] = s_f[sl.cl][j];
+        collide<FORCE>(a, f, out);
+        float dr = 0.0f;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            s_f[sl.cl][j] = out[j];
+            dr += S::ld(S::st(out[j], a.scale), a.inv_scale);
+        }
+        dens_cur[c] = dr;
+        if (AUDIT) audit_add<S>(a, out, am);
+    }
+    __syncthreads();
+    if (active) {
+        const uint64_t at = ODD ? i * st + cell_of(bx, wrap_small(sl.x + rcx(i), bx.nx), wrap_small(sl.y + rcy(i), bx.ny),
+                                                   wrap_small(sl.z + rcz(i), bx.nz))
+                                : opp(i) * st + c;
+        __builtin_nontemporal_store(S::st(s_f[sl.cl][i], a.scale), &F[at]);
     }
     // links into the box's own body: reduced over the block, then one atomic
     // per component into the block's copy of the sums (blocks without such a
@@ -609,14 +650,24 @@ __global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, 
     const int64_t t = d.t0 + k;
     if (t >= d.t_end) return;
     const int c = int(t & 1);
-    const T *A = static_cast<const T *>(d.f[c]);
-    T *B = static_cast<T *>(d.f[c ^ 1]);
+    T *F = static_cast<T *>(d.f);
     const int blk = int(blockIdx.x - m.fluid0[si]);
-    if (blk < d.nblk_b)
-        boundary_block<S, AUDIT, FORCE>(d.a, A, B, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
-                                        acc_set(d.acc, t), d.audit_part + size_t(d.nblk_s) * 5, blk);
-    else
-        stream_collide_block<S, AUDIT, FORCE>(d.a, A, B, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
+    // the step's parity picks the streaming direction of the in-place
+    // layout; it is the same for every block of a simulation
+    if (blk < d.nblk_b) {
+        if (c)
+            boundary_block<S, AUDIT, FORCE, true>(d.a, F, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start,
+                                                  d.nbody, acc_set(d.acc, t), d.dens[c ^ 1], d.dens[c],
+                                                  d.audit_part + size_t(d.nblk_s) * 5, blk);
+        else
+            boundary_block<S, AUDIT, FORCE, false>(d.a, F, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start,
+                                                   d.nbody, acc_set(d.acc, t), d.dens[c ^ 1], d.dens[c],
+                                                   d.audit_part + size_t(d.nblk_s) * 5, blk);
+    } else if (c) {
+        stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
+    } else {
+        stream_collide_block<S, AUDIT, FORCE, false>(d.a, F, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -705,7 +756,8 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
                                               unsigned long long *__restrict__ acc_conv,
                                               const uint8_t *__restrict__ own_old, uint8_t *__restrict__ own_new,
-                                              typename S::T *__restrict__ A, int *__restrict__ err, int blk)
+                                              typename S::T *__restrict__ A, bool after_even,
+                                              float *__restrict__ dens, int *__restrict__ err, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody GeoBody, then (fused) nbody x NACC sums
     GeoBody *gb = reinterpret_cast<GeoBody *>(lds_dyn);
@@ -717,7 +769,6 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
         return;
     }
     const Box &bx = a.box;
-    const uint64_t st = bx.stride;
     const Slot sl = slot_of(bx, cur, ids, start, nlist, 1, blk);
     const int i = sl.i;
     const bool mine = sl.valid && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 1);
@@ -748,7 +799,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
         const bool uncovered = is_body(s_oo[sl.cl][0]) && s_on[sl.cl][0] == OWN_FLUID;
         if (uncovered && i > 0 && s_on[sl.cl][i] == OWN_FLUID && is_fluid(oo)) {
             r = 0.0;
-            for (int j = 0; j < Q; ++j) r += double(S::ld(A[j * st + ncell], a.inv_scale));
+            for (int j = 0; j < Q; ++j) r += double(S::ld(A[post_slot(bx, j, nxc, nyc, nzc, after_even)], a.inv_scale));
             r += a.rho0d;
         }
         s_rho[sl.cl][i] = r;
@@ -766,7 +817,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
             if (is_fluid(old)) {
                 // covered: the body swallows the cell's populations
                 for (int j = 1; j < Q; ++j) {
-                    const double fj = S::ld(A[j * st + c], a.inv_scale);
+                    const double fj = S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)], a.inv_scale);
                     p[0] += rcx(j) * fj;
                     p[1] += rcy(j) * fj;
                     p[2] += rcz(j) * fj;
@@ -807,12 +858,20 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                     const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
                     const double w = j == 0 ? 1.0 / 3.0 : (j <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
                     const double dev = w * (rb - a.rho0d) + w * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                    A[j * st + c] = S::st(float(dev), a.scale);
+                    A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)] = S::st(float(dev), a.scale);
                 }
                 p[0] = rb * u[0];
                 p[1] = rb * u[1];
                 p[2] = rb * u[2];
                 sg = -1.0;
+            }
+            if (nb_body && old != OWN_NB_BODY) {
+                // a cell that becomes a body neighbour (or is uncovered next
+                // to one): the density its links will use in the next step,
+                // summed as the boundary kernel sums what it stores
+                float dr = 0.0f;
+                for (int j = 0; j < Q; ++j) dr += S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)], a.inv_scale);
+                dens[c] = dr;
             }
         }
         if (eb >= 0) {
@@ -844,8 +903,8 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D
     const int c = int(t & 1);
     geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.nbody <= FUSE_MAX, acc_set(d.acc, t),
                      acc_set(d.acc, t + 2), d.wca_sigma, d.wca_eps, d.mov_ids, d.mov_start, d.nmov,
-                     acc_set(d.acc, t + 1), d.own[c], d.own[c ^ 1], static_cast<typename S::T *>(d.f[c ^ 1]), d.err,
-                     int(blockIdx.x - m.geo0[si]));
+                     acc_set(d.acc, t + 1), d.own[c], d.own[c ^ 1], static_cast<typename S::T *>(d.f), c == 0,
+                     d.dens[c], d.err, int(blockIdx.x - m.geo0[si]));
 }
 
 // ---------------------------------------------------------------------------
@@ -889,15 +948,27 @@ __global__ __launch_bounds__(BLOCK) void k_body_cells(Box bx, const DevBody *__r
     }
 }
 
+// coordinates of cell c
+__device__ __forceinline__ void coords(const Box &bx, uint32_t c, int &x, int &y, int &z)
+{
+    x = int(c % uint32_t(bx.nx));
+    const uint32_t yz = c / uint32_t(bx.nx);
+    y = int(yz % uint32_t(bx.ny));
+    z = int(yz / uint32_t(bx.ny));
+}
+
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_audit(StepArgs a, const typename S::T *__restrict__ A,
-                                                 const uint8_t *__restrict__ own, double *__restrict__ part)
+                                                 const uint8_t *__restrict__ own, bool after_even,
+                                                 double *__restrict__ part)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (c < a.box.n && is_fluid(own[c])) {
+        int x, y, z;
+        coords(a.box, c, x, y, z);
         for (int i = 0; i < Q; ++i) {
-            const double v = S::ld(A[i * a.box.stride + c], a.inv_scale);
+            const double v = S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
             am[0] += v;
             am[1] += cx(i) * v;
             am[2] += cy(i) * v;
@@ -932,8 +1003,9 @@ __global__ __launch_bounds__(BLOCK) void k_audit_final(const double *__restrict_
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::T *__restrict__ A,
-                                                  const uint8_t *__restrict__ own, double *__restrict__ rho,
-                                                  double *__restrict__ u, uint8_t *__restrict__ own_out)
+                                                  const uint8_t *__restrict__ own, bool after_even,
+                                                  double *__restrict__ rho, double *__restrict__ u,
+                                                  uint8_t *__restrict__ own_out)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.box.n) return;
@@ -945,8 +1017,10 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
         return;
     }
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    int x, y, z;
+    coords(a.box, c, x, y, z);
     for (int i = 0; i < Q; ++i) {
-        const double v = S::ld(A[i * a.box.stride + c], a.inv_scale);
+        const double v = S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
         r += v;
         j[0] += cx(i) * v;
         j[1] += cy(i) * v;
@@ -957,24 +1031,50 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
     for (int k = 0; k < 3; ++k) u[k * size_t(a.box.n) + c] = (j[k] - 0.5 * double(a.g[k])) / r;
 }
 
+// Population i of every cell as FP64 (solid cells read 0), and back.  Each
+// (i, cell) pair owns one slot of the in-place layout, so these are
+// permutations of the buffer.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_plane_to_f64(StepArgs a, const typename S::T *__restrict__ A,
-                                                        const uint8_t *__restrict__ own, int i,
+                                                        const uint8_t *__restrict__ own, bool after_even, int i,
                                                         double *__restrict__ out)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.box.n) return;
-    out[c] = is_fluid(own[c]) ? wgt(i) * a.rho0d + double(S::ld(A[i * a.box.stride + c], a.inv_scale)) : 0.0;
+    int x, y, z;
+    coords(a.box, c, x, y, z);
+    out[c] = is_fluid(own[c])
+                 ? wgt(i) * a.rho0d + double(S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale))
+                 : 0.0;
 }
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_plane_from_f64(StepArgs a, typename S::T *__restrict__ A,
-                                                          const uint8_t *__restrict__ own, int i,
+                                                          const uint8_t *__restrict__ own, bool after_even, int i,
                                                           const double *__restrict__ in)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.box.n) return;
-    A[i * a.box.stride + c] = is_fluid(own[c]) ? S::st(float(in[c] - wgt(i) * a.rho0d), a.scale) : S::st(0.0f, a.scale);
+    int x, y, z;
+    coords(a.box, c, x, y, z);
+    A[post_slot(a.box, i, x, y, z, after_even)] =
+        is_fluid(own[c]) ? S::st(float(in[c] - wgt(i) * a.rho0d), a.scale) : S::st(0.0f, a.scale);
+}
+
+// Densities (sum of stored deviations, in the boundary kernel's order) of
+// every cell next to a body, for the links of the next step.
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_dens(StepArgs a, const typename S::T *__restrict__ A,
+                                                const uint8_t *__restrict__ own, bool after_even,
+                                                float *__restrict__ dens)
+{
+    const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= a.box.n || own[c] != OWN_NB_BODY) return;
+    int x, y, z;
+    coords(a.box, c, x, y, z);
+    float dr = 0.0f;
+    for (int i = 0; i < Q; ++i) dr += S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
+    dens[c] = dr;
 }
 
 // bit i of mask[c] set when fluid cell c has a solid source c - c_i
@@ -1060,66 +1160,86 @@ hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int si
 }
 
 template <class S>
-static hipError_t launch_audit_t(const StepArgs &a, const void *A, const uint8_t *own, double *part, double *out,
-                                 int *err, hipStream_t s)
+static hipError_t launch_audit_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, double *part,
+                                 double *out, int *err, hipStream_t s)
 {
     const int nblk = int((a.box.n + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_audit<S>, dim3(nblk), dim3(BLOCK), 0, s, a, static_cast<const typename S::T *>(A), own,
-                       part);
+                       after_even, part);
     hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, s, part, nblk, out, err);
     return hipGetLastError();
 }
 
-hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, double *part,
-                        double *out, int *err, hipStream_t s)
+hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+                        double *part, double *out, int *err, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_audit_t<StF16>(a, A, own, part, out, err, s);
-    case 2: return launch_audit_t<StBF16>(a, A, own, part, out, err, s);
-    default: return launch_audit_t<StF32>(a, A, own, part, out, err, s);
+    case 1: return launch_audit_t<StF16>(a, A, own, after_even, part, out, err, s);
+    case 2: return launch_audit_t<StBF16>(a, A, own, after_even, part, out, err, s);
+    default: return launch_audit_t<StF32>(a, A, own, after_even, part, out, err, s);
     }
 }
 
 template <class S>
-static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, double *rho, double *u,
-                                  uint8_t *own_out, hipStream_t s)
+static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, double *rho,
+                                  double *u, uint8_t *own_out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fields<S>, dim3((a.box.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
-                       static_cast<const typename S::T *>(A), own, rho, u, own_out);
+                       static_cast<const typename S::T *>(A), own, after_even, rho, u, own_out);
     return hipGetLastError();
 }
 
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, double *rho, double *u,
-                         uint8_t *own_out, hipStream_t s)
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+                         double *rho, double *u, uint8_t *own_out, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_fields_t<StF16>(a, A, own, rho, u, own_out, s);
-    case 2: return launch_fields_t<StBF16>(a, A, own, rho, u, own_out, s);
-    default: return launch_fields_t<StF32>(a, A, own, rho, u, own_out, s);
+    case 1: return launch_fields_t<StF16>(a, A, own, after_even, rho, u, own_out, s);
+    case 2: return launch_fields_t<StBF16>(a, A, own, after_even, rho, u, own_out, s);
+    default: return launch_fields_t<StF32>(a, A, own, after_even, rho, u, own_out, s);
     }
 }
 
 template <class S>
-static hipError_t launch_plane_t(const StepArgs &a, void *A, const uint8_t *own, int i, double *buf, int to_f64,
-                                 hipStream_t s)
+static hipError_t launch_plane_t(const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i, double *buf,
+                                 int to_f64, hipStream_t s)
 {
     using T = typename S::T;
     const dim3 g((a.box.n + BLOCK - 1) / BLOCK);
     if (to_f64)
-        hipLaunchKernelGGL(k_plane_to_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<const T *>(A), own, i, buf);
+        hipLaunchKernelGGL(k_plane_to_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<const T *>(A), own, after_even, i,
+                           buf);
     else
-        hipLaunchKernelGGL(k_plane_from_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<T *>(A), own, i,
+        hipLaunchKernelGGL(k_plane_from_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<T *>(A), own, after_even, i,
                            static_cast<const double *>(buf));
     return hipGetLastError();
 }
 
-hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, int i, double *buf, int to_f64,
-                        hipStream_t s)
+hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i,
+                        double *buf, int to_f64, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_plane_t<StF16>(a, A, own, i, buf, to_f64, s);
-    case 2: return launch_plane_t<StBF16>(a, A, own, i, buf, to_f64, s);
-    default: return launch_plane_t<StF32>(a, A, own, i, buf, to_f64, s);
+    case 1: return launch_plane_t<StF16>(a, A, own, after_even, i, buf, to_f64, s);
+    case 2: return launch_plane_t<StBF16>(a, A, own, after_even, i, buf, to_f64, s);
+    default: return launch_plane_t<StF32>(a, A, own, after_even, i, buf, to_f64, s);
+    }
+}
+
+template <class S>
+static hipError_t launch_dens_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dens<S>, dim3((a.box.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
+                       static_cast<const typename S::T *>(A), own, after_even, dens);
+    return hipGetLastError();
+}
+
+hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+                       hipStream_t s)
+{
+    switch (storage) {
+    case 1: return launch_dens_t<StF16>(a, A, own, after_even, dens, s);
+    case 2: return launch_dens_t<StBF16>(a, A, own, after_even, dens, s);
+    default: return launch_dens_t<StF32>(a, A, own, after_even, dens, s);
     }
 }
 

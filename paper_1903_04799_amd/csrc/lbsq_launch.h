@@ -20,14 +20,17 @@ struct StepArgs {
 constexpr int MAXSIM = 64;
 
 // One simulation as the step kernels see it.  The kernels of step k of a
-// launch sequence advance time level t = t0 + k, read from buffers [t & 1]
-// and written to buffers [(t & 1) ^ 1]; steps with t >= t_end are skipped.
+// launch sequence advance time level t = t0 + k: populations in place in f
+// (streaming direction by the parity of t), owners and bodies read from
+// [t & 1] and written to [(t & 1) ^ 1], link densities read from dens[(t & 1)
+// ^ 1] and written to dens[t & 1]; steps with t >= t_end are skipped.
 // Force sums: set t % 3 collects step t's momentum exchange (and already
 // holds the conversion force of the previous move), set (t+1) % 3 receives
 // the conversion force of this move, set (t+2) % 3 is zeroed.
 struct SimDesc {
     StepArgs a;
-    void *f[2];
+    void *f;  // the population buffer (in-place layout)
+    float *dens[2];
     uint8_t *own[2];
     DevBody *bodies[2];
     unsigned long long *acc;  // NACCSET sets of ACCSET_SIZE integers
@@ -81,12 +84,16 @@ hipError_t launch_batch_step(int storage, const BatchLaunch &L);
 hipError_t launch_classify(const Box &bx, uint8_t *own, hipStream_t s);
 hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int side, uint8_t *own, int check,
                              int *err, hipStream_t s);
-hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, double *part,
-                        double *out, int *err, hipStream_t s);
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, double *rho, double *u,
-                         uint8_t *own_out, hipStream_t s);
-hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, int i, double *buf, int to_f64,
-                        hipStream_t s);
+// Readouts of the state after a completed step; after_even tells the
+// in-place layout (the last step's index was even).
+hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+                        double *part, double *out, int *err, hipStream_t s);
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+                         double *rho, double *u, uint8_t *own_out, hipStream_t s);
+hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i,
+                        double *buf, int to_f64, hipStream_t s);
+hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+                       hipStream_t s);
 hipError_t launch_link_mask(const Box &bx, const uint8_t *own, uint32_t *mask, hipStream_t s);
 
 }  // namespace lbsq

@@ -193,7 +193,7 @@ size_t request_bytes(const lb_request *rq, int storage)
     const uint64_t stride = ((n + 255) / 256) * 256 + 256;
     const size_t es = storage == LB_STORAGE_F32 ? 4 : 2;
     const uint64_t nblk = (n + BLOCK - 1) / BLOCK;
-    size_t t = 2 * g(size_t(Q) * stride * es) + 2 * g(n) + 2 * g(MAXB * sizeof(DevBody));
+    size_t t = g(size_t(Q) * stride * es) + 2 * g(n * sizeof(float)) + 2 * g(n) + 2 * g(MAXB * sizeof(DevBody));
     t += g(4 * (MAXB + 1) * sizeof(int)) + g(sizeof(SimDesc)) + g(NACCSET * ACCSET_SIZE * sizeof(unsigned long long));
     t += g(nblk * 5 * sizeof(double)) + g(8 * sizeof(double)) + g(4 * sizeof(int));
     return t;

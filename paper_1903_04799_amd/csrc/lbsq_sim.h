@@ -14,8 +14,11 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     lbsq::StepArgs args{};
     size_t esize = 4;
-    // double-buffered state; index cur holds the current time level
-    void *f[2] = {nullptr, nullptr};
+    // populations in place (one buffer); owners and bodies double-buffered,
+    // index cur holding the current time level; link densities of the
+    // previous and current step
+    void *f = nullptr;
+    float *d_dens[2] = {nullptr, nullptr};
     uint8_t *own[2] = {nullptr, nullptr};
     lbsq::DevBody *d_bodies[2] = {nullptr, nullptr};
     int cur = 0;  // always steps & 1
