@@ -267,6 +267,8 @@ int lb_create(const lb_params *p, lb_sim **out)
     const double lo = 1.0 / (p->magic / (1.0 / le - 0.5) + 0.5);
     if (!(le > 0.0 && le < 2.0 && lo > 0.0 && lo < 2.0)) return LB_EINVAL;
     if (!(p->wca_sigma > 0.0) || p->wca_eps < 0.0) return LB_EINVAL;
+    // one population plane must stay below 4 GiB (32-bit offsets in the kernels)
+    if (plane_stride(n) * (p->storage == LB_STORAGE_F32 ? 4 : 2) > (uint64_t(1) << 32)) return LB_EINVAL;
     if ((p->alloc == nullptr) != (p->free == nullptr)) return LB_EINVAL;
 
     lb_sim *s = new (std::nothrow) lb_sim();

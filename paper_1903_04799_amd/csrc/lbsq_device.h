@@ -11,6 +11,17 @@
 
 namespace lbsq {
 
+// Pointers known to address device global memory.  Pointers read from a
+// descriptor in memory are generic otherwise, which costs flat loads and
+// 64-bit address arithmetic on the hot path.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p)
+{
+    return (gptr<T>)p;
+}
+
 constexpr int Q = 19;
 constexpr int BLOCK = 256;
 constexpr int MAXB = 252;

@@ -233,6 +233,39 @@ __device__ __forceinline__ void audit_add(const StepArgs &a, const float (&out)[
 // which sits in F[ibar][s] before an even step and in F[i][x] before an odd
 // one; neither slot is written by anyone else in the step.
 
+// Element idx of a population plane P, addressed by a 32-bit byte offset from
+// the plane's (uniform) base: the loads and stores then take the scalar-base,
+// vector-offset form.  Planes are below 4 GiB (checked at creation).
+template <class S>
+__device__ __forceinline__ float ld_plane(gptr<const typename S::T> P, uint32_t idx, float inv)
+{
+    using T = typename S::T;
+    return S::ld(*(gptr<const T>)((gptr<const char>)P + idx * uint32_t(sizeof(T))), inv);
+}
+template <class S>
+__device__ __forceinline__ void st_plane_nt(gptr<typename S::T> P, uint32_t idx, float v, float scale)
+{
+    using T = typename S::T;
+    __builtin_nontemporal_store(S::st(v, scale), (gptr<T>)((gptr<char>)P + idx * uint32_t(sizeof(T))));
+}
+
+// The Q plane bases of the buffer, computed in uniform control flow and
+// pinned in scalar registers by an empty asm (otherwise the compiler folds
+// them into per-lane 64-bit addresses).
+template <class T>
+struct Planes {
+    gptr<T> p[Q];
+    __device__ __forceinline__ Planes(gptr<T> F, uint64_t st)
+    {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            gptr<char> b = (gptr<char>)(F + i * st);
+            asm volatile("" : "+s"(b));
+            p[i] = (gptr<T>)b;
+        }
+    }
+};
+
 // Slot of the post-collision population f*_j of cell (x, y, z) between steps,
 // after an even (after_even) or odd step.
 __device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y, int z, bool after_even)
@@ -246,12 +279,11 @@ __device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y
 // the hot loop: every fluid cell without a body neighbour
 
 template <class S, bool AUDIT, bool FORCE, bool ODD>
-__device__ __forceinline__ void stream_collide_block(const StepArgs &a, typename S::T *F,
-                                                     const uint8_t *__restrict__ own, double *__restrict__ audit_part,
-                                                     uint32_t blk)
+__device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
+                                                     double *__restrict__ audit_part, uint32_t blk)
 {
+    const Planes<typename S::T> P(F, a.box.stride);
     const uint32_t idx = blk * BLOCK + threadIdx.x;
-    const uint64_t st = a.box.stride;
     const uint8_t o = idx < a.box.n ? own[idx] : OWN_WALL;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (o == OWN_FLUID || o == OWN_NB_WALL) {
@@ -259,25 +291,27 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, typename
         float f[Q];
         if (o == OWN_FLUID) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                f[i] = S::ld(ODD ? F[opp(i) * st + nb.src(i)] : F[i * st + idx], a.inv_scale);
+            for (int i = 0; i < Q; ++i) {
+                if (ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i), a.inv_scale);
+                else f[i] = ld_plane<S>(P.p[i], idx, a.inv_scale);
+            }
         } else {
             // no-slip walls: a population that would come from a wall is the
             // cell's own opposite post-collision population
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const uint32_t s = nb.src(i);
-                const bool fl = is_fluid(own[s]);
-                const uint64_t at = ODD ? (fl ? opp(i) * st + s : i * st + idx) : (fl ? i * st + idx : opp(i) * st + s);
-                f[i] = S::ld(F[at], a.inv_scale);
+                if (ODD == is_fluid(own[s])) f[i] = ld_plane<S>(P.p[opp(i)], s, a.inv_scale);
+                else f[i] = ld_plane<S>(P.p[i], idx, a.inv_scale);
             }
         }
         float out[Q];
         collide<FORCE>(a, f, out);
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            __builtin_nontemporal_store(S::st(out[i], a.scale),
-                                        &F[ODD ? i * st + nb.src(opp(i)) : opp(i) * st + idx]);
+        for (int i = 0; i < Q; ++i) {
+            if (ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i], a.scale);
+            else st_plane_nt<S>(P.p[opp(i)], idx, out[i], a.scale);
+        }
         if (AUDIT) audit_add<S>(a, out, am);
     }
     if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
@@ -528,12 +562,11 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
 // collision.  Momentum exchange: integer sums, reduced over the block for
 // the box's own body.
 template <class S, bool AUDIT, bool FORCE, bool ODD>
-__device__ __forceinline__ void boundary_block(const StepArgs &a, typename S::T *F, const uint8_t *__restrict__ own,
+__device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
                                                const DevBody *__restrict__ cur, int nbody,
                                                const int *__restrict__ ids, const int *__restrict__ start, int nlist,
-                                               unsigned long long *__restrict__ acc,
-                                               const float *__restrict__ dens_prev, float *__restrict__ dens_cur,
-                                               double *__restrict__ audit_part, int blk)
+                                               unsigned long long *__restrict__ acc, gptr<const float> dens_prev,
+                                               gptr<float> dens_cur, double *__restrict__ audit_part, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody LinkBody entries
     LinkBody *lb = reinterpret_cast<LinkBody *>(lds_dyn);
@@ -650,23 +683,24 @@ __global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, 
     const int64_t t = d.t0 + k;
     if (t >= d.t_end) return;
     const int c = int(t & 1);
-    T *F = static_cast<T *>(d.f);
+    const gptr<T> F = as_global(static_cast<T *>(d.f));
+    const gptr<const uint8_t> own = as_global(static_cast<const uint8_t *>(d.own[c]));
     const int blk = int(blockIdx.x - m.fluid0[si]);
     // the step's parity picks the streaming direction of the in-place
     // layout; it is the same for every block of a simulation
     if (blk < d.nblk_b) {
+        const gptr<const float> dp = as_global(static_cast<const float *>(d.dens[c ^ 1]));
+        const gptr<float> dc = as_global(d.dens[c]);
         if (c)
-            boundary_block<S, AUDIT, FORCE, true>(d.a, F, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start,
-                                                  d.nbody, acc_set(d.acc, t), d.dens[c ^ 1], d.dens[c],
-                                                  d.audit_part + size_t(d.nblk_s) * 5, blk);
+            boundary_block<S, AUDIT, FORCE, true>(d.a, F, own, d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
+                                                  acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
         else
-            boundary_block<S, AUDIT, FORCE, false>(d.a, F, d.own[c], d.bodies[c], d.nbody, d.all_ids, d.all_start,
-                                                   d.nbody, acc_set(d.acc, t), d.dens[c ^ 1], d.dens[c],
-                                                   d.audit_part + size_t(d.nblk_s) * 5, blk);
+            boundary_block<S, AUDIT, FORCE, false>(d.a, F, own, d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
+                                                   acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
     } else if (c) {
-        stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
+        stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));
     } else {
-        stream_collide_block<S, AUDIT, FORCE, false>(d.a, F, d.own[c], d.audit_part, uint32_t(blk - d.nblk_b));
+        stream_collide_block<S, AUDIT, FORCE, false>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));
     }
 }
 
@@ -755,9 +789,9 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                                               unsigned long long *__restrict__ acc_clear, double sigma, double eps,
                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
                                               unsigned long long *__restrict__ acc_conv,
-                                              const uint8_t *__restrict__ own_old, uint8_t *__restrict__ own_new,
-                                              typename S::T *__restrict__ A, bool after_even,
-                                              float *__restrict__ dens, int *__restrict__ err, int blk)
+                                              gptr<const uint8_t> own_old, gptr<uint8_t> own_new,
+                                              gptr<typename S::T> A, bool after_even, gptr<float> dens,
+                                              int *__restrict__ err, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody GeoBody, then (fused) nbody x NACC sums
     GeoBody *gb = reinterpret_cast<GeoBody *>(lds_dyn);
@@ -903,8 +937,9 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D
     const int c = int(t & 1);
     geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.nbody <= FUSE_MAX, acc_set(d.acc, t),
                      acc_set(d.acc, t + 2), d.wca_sigma, d.wca_eps, d.mov_ids, d.mov_start, d.nmov,
-                     acc_set(d.acc, t + 1), d.own[c], d.own[c ^ 1], static_cast<typename S::T *>(d.f), c == 0,
-                     d.dens[c], d.err, int(blockIdx.x - m.geo0[si]));
+                     acc_set(d.acc, t + 1), as_global(static_cast<const uint8_t *>(d.own[c])), as_global(d.own[c ^ 1]),
+                     as_global(static_cast<typename S::T *>(d.f)), c == 0, as_global(d.dens[c]), d.err,
+                     int(blockIdx.x - m.geo0[si]));
 }
 
 // ---------------------------------------------------------------------------
