@@ -40,6 +40,19 @@ void dev_free(lb_sim *s, void *p)
     else (void)hipFree(p);
 }
 
+// Multiplier m and shift s with floor(v / d) = umulhi(v, m) >> s for every
+// v < 2^31 (d >= 2): with l = ceil(log2 d), m = ceil(2^(31+l) / d) < 2^32
+// and the rounding excess m d - 2^(31+l) < 2^l keeps v m / 2^(31+l) within
+// 1/d of v/d.
+void magic_divisor(uint32_t d, uint32_t &m, uint32_t &s)
+{
+    int l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint64_t S = 31 + uint64_t(l);
+    m = uint32_t(((uint64_t(1) << S) + d - 1) / d);
+    s = uint32_t(S - 32);
+}
+
 // Half-width of a body's box around the floor of its position.  The cells
 // of a body lie within ceil(R) of that floor, its neighbour cells within
 // ceil(R) + 1, and in one step (|v| < 1) every owner or flag change stays
@@ -73,18 +86,63 @@ int sync_check(lb_sim *s)
 
 int upload_desc(lb_sim *s);
 
-// Block ranges of the bodies' boxes (all bodies, and the moving ones).
+// The cells of a body's box that can be fluid cells next to the body for
+// some position of the body within its floor cell: relative offsets r
+// (|r_k| <= H), packed as three 10-bit fields biased by 512.  A cell
+// qualifies when it is outside the sphere for some offset p of the centre in
+// [0, 1]^3 (its farthest point of that cube lies beyond R) and one of its
+// D3Q19 neighbours is inside for some p (the nearest point lies within R);
+// the tolerance keeps the set a superset of what the exact fixed-point test
+// can produce.
+std::vector<uint32_t> shell_cells(const DevBody &B)
+{
+    const double R = double(B.Rq) / 1048576.0, R2 = R * R, tol = 1e-6 * (1.0 + R2);
+    std::vector<uint32_t> out;
+    for (int rz = -B.H; rz <= B.H; ++rz)
+        for (int ry = -B.H; ry <= B.H; ++ry)
+            for (int rx = -B.H; rx <= B.H; ++rx) {
+                const int r[3] = {rx, ry, rz};
+                double far2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double c = r[k] + 0.5;
+                    far2 += std::max(c * c, (c - 1.0) * (c - 1.0));
+                }
+                if (far2 <= R2 - tol) continue;  // inside for every position
+                bool near = false;
+                for (int j = 1; j < Q && !near; ++j) {
+                    const int cj[3] = {cx(j), cy(j), cz(j)};
+                    double d2 = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        const double c = r[k] + cj[k] + 0.5;
+                        const double d = c < 0.0 ? -c : (c > 1.0 ? c - 1.0 : 0.0);
+                        d2 += d * d;
+                    }
+                    near = d2 <= R2 + tol;
+                }
+                if (near)
+                    out.push_back(uint32_t(rx + 512) | (uint32_t(ry + 512) << 10) | (uint32_t(rz + 512) << 20));
+            }
+    return out;
+}
+
+// Work lists: the moving bodies and the block ranges of their (grown) boxes
+// for the geometry kernel; every body, the block ranges of its shell cells
+// and where they sit in the shell array for the fluid kernel.
 int rebuild_lists(lb_sim *s)
 {
     const int nb = int(s->bodies.size());
-    std::vector<int> mov_ids, mov_start(1, 0), all_ids, all_start(1, 0);
+    std::vector<int> mov_ids, mov_start(1, 0), all_ids, all_start(1, 0), all_base, all_count;
+    std::vector<uint32_t> shell;
     for (int b = 0; b < nb; ++b) {
-        const int side = 2 * s->bodies[b].H + 1;
+        const std::vector<uint32_t> sh = shell_cells(s->bodies[b]);
         all_ids.push_back(b);
-        all_start.push_back(all_start.back() + int((uint64_t(side) * side * side + CPB - 1) / CPB));
+        all_base.push_back(int(shell.size()));
+        all_count.push_back(int(sh.size()));
+        shell.insert(shell.end(), sh.begin(), sh.end());
+        all_start.push_back(all_start.back() + int((sh.size() + CPB - 1) / CPB));
         if (s->bodies[b].mode == LB_FIXED) continue;
         // the geometry kernel walks the box grown by one cell on each side
-        const int gside = side + 2;
+        const int gside = 2 * s->bodies[b].H + 3;
         mov_ids.push_back(b);
         mov_start.push_back(mov_start.back() + int((uint64_t(gside) * gside * gside + CPB - 1) / CPB));
     }
@@ -95,7 +153,35 @@ int rebuild_lists(lb_sim *s)
     packed.insert(packed.end(), mov_start.begin(), mov_start.end());
     packed.insert(packed.end(), all_ids.begin(), all_ids.end());
     packed.insert(packed.end(), all_start.begin(), all_start.end());
+    packed.insert(packed.end(), all_base.begin(), all_base.end());
+    packed.insert(packed.end(), all_count.begin(), all_count.end());
     if (hipMemcpy(s->d_lists, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return LB_EDEVICE;
+    if (shell.size() > s->shell_cap) {
+        dev_free(s, s->d_shell);
+        s->d_shell = static_cast<uint32_t *>(dev_alloc(s, shell.size() * sizeof(uint32_t)));
+        if (!s->d_shell) return LB_ENOMEM;
+        s->shell_cap = shell.size();
+    }
+    if (!shell.empty() &&
+        hipMemcpy(s->d_shell, shell.data(), shell.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return LB_EDEVICE;
+    // one record per boundary block: its body, its first shell cell, how
+    // many cells it takes
+    std::vector<int4> info;
+    for (int m = 0; m < nb; ++m)
+        for (int j = all_start[m]; j < all_start[m + 1]; ++j) {
+            const int first = (j - all_start[m]) * CPB;
+            info.push_back(make_int4(all_ids[m], all_base[m] + first, std::min(CPB, all_count[m] - first), m));
+        }
+    if (info.size() > s->blkinfo_cap) {
+        dev_free(s, s->d_blkinfo);
+        s->d_blkinfo = static_cast<int4 *>(dev_alloc(s, info.size() * sizeof(int4)));
+        if (!s->d_blkinfo) return LB_ENOMEM;
+        s->blkinfo_cap = info.size();
+    }
+    if (!info.empty() &&
+        hipMemcpy(s->d_blkinfo, info.data(), info.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
         return LB_EDEVICE;
     // audit partials: one per streaming block and one per boundary block
     const size_t need = size_t(nblocks(s->args.box.n)) + size_t(s->nblk_all);
@@ -128,6 +214,10 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
     d.mov_start = s->d_lists + s->nmov;
     d.all_ids = s->d_lists + 2 * s->nmov + 1;
     d.all_start = s->d_lists + 2 * s->nmov + 1 + d.nbody;
+    d.all_base = s->d_lists + 2 * s->nmov + 2 + 2 * d.nbody;
+    d.all_count = s->d_lists + 2 * s->nmov + 2 + 3 * d.nbody;
+    d.shell = s->d_shell;
+    d.blkinfo = s->d_blkinfo;
     d.audit_part = s->d_audit_part;
     d.err = s->d_err;
     d.wca_sigma = s->p.wca_sigma;
@@ -243,6 +333,8 @@ int lb_destroy(lb_sim *s)
         dev_free(s, s->d_bodies[k]);
     }
     dev_free(s, s->d_lists);
+    dev_free(s, s->d_shell);
+    dev_free(s, s->d_blkinfo);
     dev_free(s, s->d_desc);
     dev_free(s, s->d_batch_desc);
     dev_free(s, s->d_acc);
@@ -282,6 +374,8 @@ int lb_create(const lb_params *p, lb_sim **out)
     bx.nz = p->nz;
     bx.n = uint32_t(n);
     bx.stride = plane_stride(n);
+    magic_divisor(uint32_t(p->nx), bx.mx, bx.sx);
+    magic_divisor(uint32_t(p->ny), bx.my, bx.sy);
     s->args.lam_e = float(le);
     s->args.lam_o = float(lo);
     s->args.rho0 = float(p->rho0);
@@ -298,7 +392,7 @@ int lb_create(const lb_params *p, lb_sim **out)
         s->own[k] = static_cast<uint8_t *>(dev_alloc(s, n));
         s->d_bodies[k] = static_cast<DevBody *>(dev_alloc(s, MAXB * sizeof(DevBody)));
     }
-    s->d_lists = static_cast<int *>(dev_alloc(s, 4 * (MAXB + 1) * sizeof(int)));
+    s->d_lists = static_cast<int *>(dev_alloc(s, 6 * (MAXB + 1) * sizeof(int)));
     s->d_acc = static_cast<unsigned long long *>(dev_alloc(s, NACCSET * ACCSET_SIZE * sizeof(unsigned long long)));
     s->d_audit_part = static_cast<double *>(dev_alloc(s, size_t(nblocks(n)) * 5 * sizeof(double)));
     s->audit_blocks = size_t(nblocks(n));
@@ -357,6 +451,7 @@ int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
     const Box &bx = s->args.box;
     DevBody B;
     std::memset(&B, 0, sizeof(B));
+    if (!(q->R < 500.0)) return LB_EINVAL;  // shell offsets are packed in 10 bits
     B.H = body_half_width(q->R);
     const int side = 2 * B.H + 1;
     if (side + 2 > std::min(bx.nx, std::min(bx.ny, bx.nz))) return LB_EGEOM;

@@ -178,7 +178,12 @@ struct Box {
     int nx, ny, nz;
     uint32_t n;       // cells
     uint64_t stride;  // elements between population planes
+    // division by nx and ny as a multiply and shift, exact for dividends
+    // below 2^31: q = umulhi(v, m) >> s
+    uint32_t mx, sx, my, sy;
 };
+
+__device__ __forceinline__ uint32_t div_magic(uint32_t v, uint32_t m, uint32_t s) { return __umulhi(v, m) >> s; }
 
 // Minimum image of a real difference in a box of length L (|d| < 1.5 L).
 __device__ __forceinline__ double min_image(double d, int L)

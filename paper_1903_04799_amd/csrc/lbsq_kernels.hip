@@ -130,10 +130,10 @@ struct Nbr {
     __device__ __forceinline__ Nbr(const Box &bx, uint32_t i) : idx(i)
     {
         const uint32_t nx = bx.nx, ny = bx.ny, nz = bx.nz, pl = nx * ny;
-        x = i % nx;
-        const uint32_t yz = i / nx;
-        y = yz % ny;
-        z = yz / ny;
+        const uint32_t yz = div_magic(i, bx.mx, bx.sx);
+        x = i - yz * nx;
+        z = div_magic(yz, bx.my, bx.sy);
+        y = yz - z * ny;
         oxm = x == 0 ? nx - 1 : uint32_t(-1);
         oxp = x == nx - 1 ? uint32_t(1) - nx : 1u;
         oym = y == 0 ? (ny - 1) * nx : uint32_t(0) - nx;
@@ -218,6 +218,60 @@ __device__ __forceinline__ void audit_add(const StepArgs &a, const float (&out)[
         am[3] += cz(i) * v;
     }
     am[4] = 1.0;
+}
+
+// The same TRT collision for one direction i of a cell, by the thread that
+// owns that direction (the boundary kernel's layout); f holds the cell's 19
+// incoming populations in shared memory.  For the pair (i, ibar) both
+// threads evaluate the shared symmetric part identically and the
+// antisymmetric part with opposite signs.
+template <bool FORCE>
+__device__ __forceinline__ float collide_one(const StepArgs &a, const float *f, int i)
+{
+    float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const float v = f[k];
+        drho += v;
+        if (cx(k)) jx += cx(k) * v;
+        if (cy(k)) jy += cy(k) * v;
+        if (cz(k)) jz += cz(k) * v;
+    }
+    if (FORCE) {
+        jx += 0.5f * a.g[0];
+        jy += 0.5f * a.g[1];
+        jz += 0.5f * a.g[2];
+    }
+    const float rho = a.rho0 + drho;
+    const float ir = 1.0f / rho;
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float le = a.lam_e, lo = a.lam_o;
+    const float w = i == 0 ? wgtf(0) : (i <= 6 ? wgtf(1) : wgtf(7));
+    const float fi = f[i];
+    float out;
+    if (i == 0) {
+        out = fi - le * (fi - w * (drho - 1.5f * rho * usq));
+    } else {
+        const float fb = f[opp(i)];
+        const float cu = rcx(i) * ux + rcy(i) * uy + rcz(i) * uz;
+        const float ep = w * (drho + rho * (4.5f * cu * cu - 1.5f * usq));
+        const float em = w * rho * 3.0f * cu;
+        const float fp = 0.5f * (fi + fb), fm = 0.5f * (fi - fb);
+        out = fi - le * (fp - ep) - lo * (fm - em);
+    }
+    if (FORCE) {
+        const float ug = ux * a.g[0] + uy * a.g[1] + uz * a.g[2];
+        const float ce = 1.0f - 0.5f * le, co = 1.0f - 0.5f * lo;
+        if (i == 0) {
+            out += ce * w * (-3.0f * ug);
+        } else {
+            const float cu = rcx(i) * ux + rcy(i) * uy + rcz(i) * uz;
+            const float cg = rcx(i) * a.g[0] + rcy(i) * a.g[1] + rcz(i) * a.g[2];
+            out += ce * (w * (9.0f * cu * cg - 3.0f * ug)) + co * (3.0f * w * cg);
+        }
+    }
+    return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,9 +381,21 @@ __device__ void rotate_by(double e[3], const double w[3])
     const double k[3] = {w[0] / th, w[1] / th, w[2] / th};
     const double kxe[3] = {k[1] * e[2] - k[2] * e[1], k[2] * e[0] - k[0] * e[2], k[0] * e[1] - k[1] * e[0]};
     const double ke = k[0] * e[0] + k[1] * e[1] + k[2] * e[2];
-    const double c = cos(th), s = sin(th);
+    // the per-step angle is tiny: a short series gives sin, cos and 1 - cos
+    // to double precision without the library's argument reduction
+    double s, c, omc;
+    if (th < 1e-2) {
+        const double t2 = th * th;
+        s = th * (1.0 - t2 / 6.0 * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0))));
+        omc = t2 / 2.0 * (1.0 - t2 / 12.0 * (1.0 - t2 / 30.0 * (1.0 - t2 / 56.0)));
+        c = 1.0 - omc;
+    } else {
+        s = sin(th);
+        c = cos(th);
+        omc = 1.0 - c;
+    }
     double o[3];
-    for (int a = 0; a < 3; ++a) o[a] = e[a] * c + kxe[a] * s + k[a] * ke * (1.0 - c);
+    for (int a = 0; a < 3; ++a) o[a] = e[a] * c + kxe[a] * s + k[a] * ke * omc;
     const double nn = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
     for (int a = 0; a < 3; ++a) e[a] = o[a] / nn;
 }
@@ -564,31 +630,24 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
 template <class S, bool AUDIT, bool FORCE, bool ODD>
 __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
                                                const DevBody *__restrict__ cur, int nbody,
-                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
+                                               const int4 *__restrict__ blkinfo, const uint32_t *__restrict__ shell,
                                                unsigned long long *__restrict__ acc, gptr<const float> dens_prev,
                                                gptr<float> dens_cur, double *__restrict__ audit_part, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody LinkBody entries
     LinkBody *lb = reinterpret_cast<LinkBody *>(lds_dyn);
-    __shared__ float s_f[CPB][Q + 1];
+    __shared__ float s_f[CPB][Q + 1], s_o[CPB][Q + 1];
+    __shared__ int s_minb[CPB];
     const Box &bx = a.box;
     const uint64_t st = bx.stride;
-    const Slot sl = slot_of(bx, cur, ids, start, nlist, 0, blk);
-    const int i = sl.i;
-    const uint32_t c = cell_of(bx, sl.x, sl.y, sl.z);
-    const bool active = sl.valid && own[c] == OWN_NB_BODY && first_box(bx, cur, ids, sl.m, sl.x, sl.y, sl.z, 0);
-    const uint32_t s = cell_of(bx, wrap_small(sl.x - rcx(i), bx.nx), wrap_small(sl.y - rcy(i), bx.ny),
-                               wrap_small(sl.z - rcz(i), bx.nz));
-    // one load per (cell, direction): the incoming population where the source
-    // is fluid, else the cell's own f*_ibar for the reflection
-    float fl = 0.0f;
-    uint8_t os = OWN_FLUID;
-    if (active) {
-        if (i > 0) os = own[s];
-        const bool from_fluid = is_fluid(os);
-        const uint64_t at = ODD ? (from_fluid ? opp(i) * st + s : i * st + c) : (from_fluid ? i * st + c : opp(i) * st + s);
-        fl = S::ld(F[at], a.inv_scale);
-    }
+    // the block's body and first shell cell (precomputed), the thread's
+    // (shell cell, direction)
+    const int4 bi = blkinfo[blk];
+    const int home = bi.x;
+    const int cl = threadIdx.x / Q, i = threadIdx.x - cl * Q;
+    const bool valid = cl < bi.z;
+    const uint32_t e = valid ? shell[bi.y + cl] : 0x20080200u;  // offset (0, 0, 0) when unused
+    // the bodies' link data, staged once per block
     for (int b = threadIdx.x; b < nbody; b += BLOCK) {
         const DevBody &D = cur[b];
         LinkBody &L = lb[b];
@@ -604,7 +663,31 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
         L.B1 = float(D.B1);
         L.beta = float(D.beta);
     }
+    if (threadIdx.x < CPB) s_minb[threadIdx.x] = 0x7fffffff;
     __syncthreads();
+    const int x = wrap_small(lb[home].ip[0] + int(e & 1023u) - 512, bx.nx);
+    const int y = wrap_small(lb[home].ip[1] + int((e >> 10) & 1023u) - 512, bx.ny);
+    const int z = wrap_small(lb[home].ip[2] + int((e >> 20) & 1023u) - 512, bx.nz);
+    const uint32_t c = cell_of(bx, x, y, z);
+    const uint32_t s = cell_of(bx, wrap_small(x - rcx(i), bx.nx), wrap_small(y - rcy(i), bx.ny),
+                               wrap_small(z - rcz(i), bx.nz));
+    // the owners and both candidate populations are loaded together: the
+    // incoming population where the source is fluid, the cell's own f*_ibar
+    // (for a reflection) otherwise
+    const uint8_t oc = valid ? own[c] : OWN_WALL;
+    const uint8_t os = (valid && i > 0) ? own[s] : OWN_FLUID;
+    float f_in = 0.0f, f_ref = 0.0f;
+    if (valid) {
+        f_in = S::ld(F[ODD ? opp(i) * st + s : i * st + c], a.inv_scale);
+        f_ref = S::ld(F[ODD ? i * st + c : opp(i) * st + s], a.inv_scale);
+    }
+    const bool cand = oc == OWN_NB_BODY;
+    const float fl = is_fluid(os) ? f_in : f_ref;
+    // a cell next to several bodies is taken by the smallest of them (the
+    // shell lists of all of them contain it)
+    if (cand && is_body(os)) atomicMin(&s_minb[cl], int(os) - 1);
+    __syncthreads();
+    const bool active = cand && s_minb[cl] == home;
     int key = -1;  // body of this thread's link
     long long v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
@@ -616,37 +699,44 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
             key = os - 1;
             float fv[6];
             int kf[3], kr[3];
-            fin = body_link(bx, lb[key], i, sl.x, sl.y, sl.z, fl, rw, fv, kf, kr);
+            fin = body_link(bx, lb[key], i, x, y, z, fl, rw, fv, kf, kr);
             for (int k = 0; k < 6; ++k) v[k] = to_fx(fv[k]);
             for (int k = 0; k < 3; ++k) {
                 v[6 + k] = kf[k];
                 v[9 + k] = kr[k];
             }
         }
-        s_f[sl.cl][i] = fin;
+        s_f[cl][i] = fin;
     }
     __syncthreads();
+    // collision, one direction per thread; the stored (rounded) values are
+    // summed for the link density of the next step and for the audit
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const typename S::T o = S::st(collide_one<FORCE>(a, s_f[cl], i), a.scale);
+        s_o[cl][i] = S::ld(o, a.inv_scale);
+        const uint64_t at = ODD ? i * st + cell_of(bx, wrap_small(x + rcx(i), bx.nx), wrap_small(y + rcy(i), bx.ny),
+                                                   wrap_small(z + rcz(i), bx.nz))
+                                : opp(i) * st + c;
+        __builtin_nontemporal_store(o, &F[at]);
+    }
+    __syncthreads();
     if (active && i == 0) {
-        float f[Q], out[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = s_f[sl.cl][j];
-        collide<FORCE>(a, f, out);
         float dr = 0.0f;
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            s_f[sl.cl][j] = out[j];
-            dr += S::ld(S::st(out[j], a.scale), a.inv_scale);
-        }
+        for (int j = 0; j < Q; ++j) dr += s_o[cl][j];
         dens_cur[c] = dr;
-        if (AUDIT) audit_add<S>(a, out, am);
-    }
-    __syncthreads();
-    if (active) {
-        const uint64_t at = ODD ? i * st + cell_of(bx, wrap_small(sl.x + rcx(i), bx.nx), wrap_small(sl.y + rcy(i), bx.ny),
-                                                   wrap_small(sl.z + rcz(i), bx.nz))
-                                : opp(i) * st + c;
-        __builtin_nontemporal_store(S::st(s_f[sl.cl][i], a.scale), &F[at]);
+        if (AUDIT) {
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const double v = s_o[cl][j];
+                am[0] += v;
+                am[1] += cx(j) * v;
+                am[2] += cy(j) * v;
+                am[3] += cz(j) * v;
+            }
+            am[4] = 1.0;
+        }
     }
     // links into the box's own body: reduced over the block, then one atomic
     // per component into the block's copy of the sums (blocks without such a
@@ -654,7 +744,6 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     // are added directly
     constexpr int slot[12] = {0, 1, 2, 3, 4, 5, 12, 13, 14, 15, 16, 17};
     unsigned long long *copy = acc + (blk % NCOPY) * (MAXB * NACC);
-    const int home = ids[sl.m];
     if (key >= 0 && key != home) {
         for (int k = 0; k < 12; ++k) atomicAdd(&copy[key * NACC + slot[k]], static_cast<unsigned long long>(v[k]));
         for (int k = 0; k < 12; ++k) v[k] = 0;
@@ -692,10 +781,10 @@ __global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, 
         const gptr<const float> dp = as_global(static_cast<const float *>(d.dens[c ^ 1]));
         const gptr<float> dc = as_global(d.dens[c]);
         if (c)
-            boundary_block<S, AUDIT, FORCE, true>(d.a, F, own, d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
+            boundary_block<S, AUDIT, FORCE, true>(d.a, F, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
                                                   acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
         else
-            boundary_block<S, AUDIT, FORCE, false>(d.a, F, own, d.bodies[c], d.nbody, d.all_ids, d.all_start, d.nbody,
+            boundary_block<S, AUDIT, FORCE, false>(d.a, F, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
                                                    acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
     } else if (c) {
         stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));

@@ -35,7 +35,10 @@ struct SimDesc {
     DevBody *bodies[2];
     unsigned long long *acc;  // NACCSET sets of ACCSET_SIZE integers
     const int *mov_ids, *mov_start;  // moving bodies and the block ranges of their boxes
-    const int *all_ids, *all_start;  // every body and theirs
+    const int *all_ids, *all_start;  // every body and the block ranges of its shell cells
+    const int *all_base, *all_count;  // where each body's shell cells sit in shell, and how many
+    const uint32_t *shell;            // packed offsets relative to the floor of the body position
+    const int4 *blkinfo;              // per boundary block: body, first shell cell, cells, list position
     double *audit_part;
     int *err;
     double wca_sigma, wca_eps;

@@ -25,7 +25,11 @@ struct lb_sim {
     lbsq::SimDesc *d_desc = nullptr;  // the step kernels' view of this simulation
     lbsq::SimDesc *d_batch_desc = nullptr;  // MAXSIM descriptors for lb_step_batch led by this handle
     std::vector<lbsq::DevBody> bodies;
-    int *d_lists = nullptr;  // mov_ids | mov_start | all_ids | all_start
+    int *d_lists = nullptr;  // mov_ids | mov_start | all_ids | all_start | all_base | all_count
+    uint32_t *d_shell = nullptr;  // packed shell-cell offsets of every body
+    size_t shell_cap = 0;
+    int4 *d_blkinfo = nullptr;  // per boundary block: body, first shell cell, cells, list position
+    size_t blkinfo_cap = 0;
     int nmov = 0, nblk_mov = 0, nblk_all = 0;
     unsigned long long *d_acc = nullptr;  // NACCSET sets of ACCSET_SIZE integer sums
     size_t audit_blocks = 0;
