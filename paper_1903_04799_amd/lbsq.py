@@ -99,6 +99,13 @@ def load():
     if not LIB_PATH.exists():
         raise ImportError("liblbsq.so not built: run `python -m paper_1903_04799_amd.build` "
                           "(expected at %s)" % LIB_PATH)
+    # torch ships its own copy of the HIP runtime under the same soname as the
+    # system one.  Loading torch first makes the library bind to that copy, so
+    # the process holds one HIP runtime and torch-allocated memory is valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(str(LIB_PATH))
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
     sig = {

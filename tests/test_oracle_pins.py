@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from tests import stokes
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -384,6 +385,51 @@ def test_P9_symmetry(beta):
     assert abs(by["F"][1] - bx["F"][0]) < 1e-9 * Fx
     assert abs(by["v"][1] - bx["v"][0]) < 1e-9 * abs(bx["v"][0])
     assert abs(by["F"][0]) < 1e-9 * Fx and abs(by["F"][2]) < 1e-9 * Fx
+
+
+# --------------------------------------------------------------------------
+# P10: the moving-wall term and the momentum exchange against textbook Stokes
+# flow.  A staircase sphere's hydrodynamic radius differs from R by a
+# fraction of a cell, so these hold to a few per cent at R = 4.  A dropped
+# rigid-body term, a wrong lever arm or sign, or a factor in the momentum
+# exchange misses by far more.  The references and the steady-state driver
+# are in tests/stokes.py.
+@pytest.mark.slow
+def test_P10_rotating_sphere_torque():
+    R, nu = 4.0, 1.0 / 6.0
+    w = 1e-2 * nu / R ** 2  # rotational Reynolds number 1e-2
+    ratio, phi = [], []
+    for L in (24, 32):
+        o = O.OracleSim(L, L, L, nu=nu)
+        o.add_body((L / 2, L / 2, L / 2), (1.0, 0.0, 0.0), R, mode=O.PRESCRIBED, w=(0.0, 0.0, w))
+        o.step(5 * stokes.box_relaxation_steps(L, nu))
+        T = o.body(0)["T"]
+        o.close()
+        assert abs(T[0]) < 1e-9 * abs(T[2]) and abs(T[1]) < 1e-9 * abs(T[2])
+        ratio.append(T[2] / (-8.0 * math.pi * nu * R ** 3 * w))
+        phi.append(stokes.volume_fraction(R, L))
+    # ratio = A (1 + c phi): A is the infinite-box torque factor, c = 1 to
+    # leading order (zero mean vorticity of a periodic field)
+    c = (ratio[0] - ratio[1]) / (ratio[1] * phi[0] - ratio[0] * phi[1])
+    A = ratio[1] / (1.0 + c * phi[1])
+    assert 0.6 < c < 1.5, (ratio, c)
+    assert abs(A - 1.0) < 0.06, (ratio, A)
+
+
+@pytest.mark.slow
+def test_P10_fixed_sphere_drag_against_hasimoto():
+    R, L, nu = 4.0, 24, 1.0 / 6.0
+    Kh = stokes.k_hasimoto(stokes.volume_fraction(R, L))
+    # superficial speed near 1e-3 nu / R: particle Reynolds number 1e-3
+    g = (1e-3 * nu / R) * 6.0 * math.pi * nu * R / (Kh * L ** 3)
+    o = O.OracleSim(L, L, L, nu=nu, g=(g, 0.0, 0.0))
+    o.add_body((L / 2, L / 2, L / 2), (1.0, 0.0, 0.0), R, mode=O.FIXED)
+    o.step(1)
+    K, balance = stokes.steady_drag(o.step, o.populations, o.set_populations, o.fields,
+                                    lambda: o.body(0)["F"][0], R, L, g, nu)
+    o.close()
+    assert abs(balance - 1.0) < 1e-3
+    assert abs(K / Kh - 1.0) < 0.03, (K, Kh)
 
 
 # --------------------------------------------------------------------------
