@@ -12,7 +12,7 @@ using namespace lbsq;
 
 namespace {
 
-constexpr int NERR = 4;
+constexpr int NERR = 4;  // error flags 0..2, then the arrival counter of the boundary blocks
 
 int nblocks(uint64_t n) { return int((n + BLOCK - 1) / BLOCK); }
 
@@ -220,6 +220,8 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
     d.blkinfo = s->d_blkinfo;
     d.audit_part = s->d_audit_part;
     d.err = s->d_err;
+    // the last error word is the boundary blocks' arrival counter
+    d.arrive = reinterpret_cast<unsigned int *>(s->d_err + (NERR - 1));
     d.wca_sigma = s->p.wca_sigma;
     d.wca_eps = s->p.wca_eps;
     d.t0 = t0;

@@ -159,8 +159,8 @@ constexpr int NACCSET = 3;
 // many blocks do not pile up on the same addresses; the body update sums them
 constexpr int NCOPY = 16;
 constexpr int ACCSET_SIZE = NCOPY * MAXB * NACC;  // integers per set
-// up to this many bodies every geometry block repeats the body update instead
-// of waiting for a separate one-block launch
+// up to this many bodies the last boundary block of the fluid launch does the
+// body update (staged in LDS); more bodies take a separate one-block launch
 constexpr int FUSE_MAX = 8;
 constexpr double FX_SCALE = 17592186044416.0;  // 2^44
 __device__ __forceinline__ long long to_fx(double v) { return __double2ll_rn(v * FX_SCALE); }

@@ -16,16 +16,17 @@
 //                     fixed-point integers.  The other blocks take every
 //                     remaining fluid cell, one thread per cell: pull
 //                     streaming and the collision (static walls reflected in
-//                     place);
-//   k_geoconv         the body update (decode of the integer force sums, WCA
-//                     eq. (wca), symplectic Euler), repeated by every block
-//                     when there are few bodies, else done before by the
-//                     one-block k_body; then, over each moving
-//                     body's box, the integer inside test at the new
-//                     positions gives new owners and neighbour flags, and the
-//                     cell conversion of Sec. "Numerical Method" refills
-//                     uncovered cells and accumulates the conversion force
-//                     eq. (consforce) for the next integration.
+//                     place).  The last boundary block of a simulation to
+//                     finish does the body update (decode of the integer
+//                     force sums, WCA eq. (wca), symplectic Euler) while the
+//                     streaming blocks still run; for many bodies the
+//                     one-block k_body does it after the launch;
+//   k_geoconv         over each moving body's box, the integer inside test
+//                     at the new positions gives new owners and neighbour
+//                     flags, and the cell conversion of Sec. "Numerical
+//                     Method" refills uncovered cells and accumulates the
+//                     conversion force eq. (consforce) for the next
+//                     integration.
 // Owners and the body table are double-buffered (time t is read while time
 // t+1 is written); force sums rotate over three accumulator sets.
 #include "lbsq_device.h"
@@ -410,12 +411,12 @@ __device__ double wca_magnitude(double r, double sigma, double eps)
     return 24.0 * eps / r * (2.0 * sr6 * sr6 - sr6);
 }
 
-// State of body b at t+1 from its state at t, the step's integer force sums
-// q (NACC values) and WCA against every other body.
+// State of body b at t+1, in place in B (which holds its state at t), from
+// the step's integer force sums q (NACC values) and WCA against every other
+// body of the table cur (time t).
 __device__ void advance_body(const Box &bx, const DevBody *__restrict__ cur, int nbody, int b, const long long *q,
                              double rho0, double sigma, double eps, DevBody &B, int *__restrict__ err)
 {
-    B = cur[b];
     const int nn[3] = {bx.nx, bx.ny, bx.nz};
     double kf[3], kr[3], p[3];
     for (int k = 0; k < 3; ++k) {
@@ -466,14 +467,17 @@ __device__ void advance_body(const Box &bx, const DevBody *__restrict__ cur, int
 }
 
 // The step's integer sums of every body: the NCOPY copies of an
-// accumulator set added up into s_q[body][k] (integer sums, so every block
-// that calls this obtains the same values).
-__device__ void gather_sums(int nbody, const unsigned long long *__restrict__ acc, long long (*s_q)[NACC])
+// accumulator set added up into s_q[body][k].  The loads are device-coherent
+// so that a block of the launch that produced the sums can read them once
+// every producer has arrived.
+__device__ void gather_sums(int nbody, unsigned long long *acc, long long (*s_q)[NACC])
 {
     for (int j = threadIdx.x; j < nbody * NACC; j += BLOCK) {
         long long t = 0;
 #pragma unroll
-        for (int c = 0; c < NCOPY; ++c) t += static_cast<long long>(acc[c * (MAXB * NACC) + j]);
+        for (int c = 0; c < NCOPY; ++c)
+            t += static_cast<long long>(
+                __hip_atomic_load(&acc[c * (MAXB * NACC) + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         s_q[j / NACC][j % NACC] = t;
     }
     __syncthreads();
@@ -495,8 +499,8 @@ __device__ __forceinline__ unsigned long long *acc_set(unsigned long long *acc, 
 }
 
 // Body update of one simulation (descriptor D[0]) by one block, for more
-// bodies than every geometry block can repeat the update for; also clears
-// the accumulator set of the step after next.
+// bodies than the fluid launch updates itself; also clears the accumulator
+// set of the step after next.
 __global__ __launch_bounds__(BLOCK) void k_body(const SimDesc *__restrict__ D, int64_t k)
 {
     __shared__ long long s_q[MAXB][NACC];
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(BLOCK) void k_body(const SimDesc *__restrict__ D, i
     const int c = int(t & 1);
     gather_sums(d.nbody, acc_set(d.acc, t), s_q);
     for (int b = threadIdx.x; b < d.nbody; b += BLOCK) {
-        DevBody B;
+        DevBody B = d.bodies[c][b];
         advance_body(d.a.box, d.bodies[c], d.nbody, b, s_q[b], d.a.rho0d, d.wca_sigma, d.wca_eps, B, d.err);
         d.bodies[c ^ 1][b] = B;
     }
@@ -627,6 +631,15 @@ __device__ __forceinline__ float body_link(const Box &bx, const LinkBody &B, int
 // fluid, reflection at walls, moving-wall bounce-back at bodies, then the
 // collision.  Momentum exchange: integer sums, reduced over the block for
 // the box's own body.
+// Add v to *p at device scope and wait until the addition has been
+// performed, so that anything the thread does afterwards (an arrival at the
+// boundary blocks' counter) is ordered after it without a cache flush.
+__device__ __forceinline__ void add_performed(unsigned long long *p, unsigned long long v)
+{
+    const unsigned long long old = __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(old));
+}
+
 template <class S, bool AUDIT, bool FORCE, bool ODD>
 __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
                                                const DevBody *__restrict__ cur, int nbody,
@@ -745,16 +758,57 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     constexpr int slot[12] = {0, 1, 2, 3, 4, 5, 12, 13, 14, 15, 16, 17};
     unsigned long long *copy = acc + (blk % NCOPY) * (MAXB * NACC);
     if (key >= 0 && key != home) {
-        for (int k = 0; k < 12; ++k) atomicAdd(&copy[key * NACC + slot[k]], static_cast<unsigned long long>(v[k]));
+        for (int k = 0; k < 12; ++k) add_performed(&copy[key * NACC + slot[k]], static_cast<unsigned long long>(v[k]));
         for (int k = 0; k < 12; ++k) v[k] = 0;
     }
     if (__syncthreads_or(key == home)) {
         __shared__ long long s_sum[12];
         block_reduce_i64<12>(v, s_sum);
         if (threadIdx.x < 12)
-            atomicAdd(&copy[home * NACC + slot[threadIdx.x]], static_cast<unsigned long long>(s_sum[threadIdx.x]));
+            add_performed(&copy[home * NACC + slot[threadIdx.x]], static_cast<unsigned long long>(s_sum[threadIdx.x]));
     }
     if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
+}
+
+// Body update of a simulation with at most FUSE_MAX bodies, by the last of
+// its boundary blocks to finish.  Every boundary block has added its link
+// momentum to the step's sums (the conversion force of the previous move is
+// already there), waited until those device-scope additions were performed,
+// and then arrives at the counter with one more device-scope addition.  The
+// block that arrives last therefore finds every sum in place: it reads them
+// with device-coherent loads, advances the bodies into the other table and
+// clears the accumulator set of the step after next, while the streaming
+// blocks still run.  No cache is flushed or invalidated (that would cost
+// the streaming blocks their cached neighbours).  It leaves the counter at
+// zero for the next step.  The new state is staged in LDS, which keeps the
+// update's registers within those of the streaming path.
+__device__ __forceinline__ void arrive_and_update(const SimDesc &d, int c, int64_t t)
+{
+    __shared__ long long s_q[FUSE_MAX][NACC];
+    __shared__ DevBody s_nb[FUSE_MAX];
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(d.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev == unsigned(d.nblk_b - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // the bodies' states at t, copied in 8-byte words by the whole block
+    static_assert(sizeof(DevBody) % sizeof(double) == 0, "body table copied in 8-byte words");
+    constexpr int W = int(sizeof(DevBody) / sizeof(double));
+    double *nb = reinterpret_cast<double *>(s_nb);
+    const double *cur = reinterpret_cast<const double *>(d.bodies[c]);
+    for (int j = threadIdx.x; j < d.nbody * W; j += BLOCK) nb[j] = cur[j];
+    gather_sums(d.nbody, acc_set(d.acc, t), s_q);
+    if (int(threadIdx.x) < d.nbody)
+        advance_body(d.a.box, d.bodies[c], d.nbody, threadIdx.x, s_q[threadIdx.x], d.a.rho0d, d.wca_sigma,
+                     d.wca_eps, s_nb[threadIdx.x], d.err);
+    __syncthreads();
+    double *nxt = reinterpret_cast<double *>(d.bodies[c ^ 1]);
+    for (int j = threadIdx.x; j < d.nbody * W; j += BLOCK) nxt[j] = nb[j];
+    clear_set(d.nbody, acc_set(d.acc, t + 2));
+    if (threadIdx.x == 0) __hip_atomic_store(d.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The update of every fluid cell of every simulation of a batch, one launch
@@ -786,6 +840,7 @@ __global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, 
         else
             boundary_block<S, AUDIT, FORCE, false>(d.a, F, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
                                                    acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
+        if (d.nbody <= FUSE_MAX) arrive_and_update(d, c, t);
     } else if (c) {
         stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));
     } else {
@@ -850,47 +905,22 @@ __device__ __forceinline__ void stage_geo(const DevBody &D, GeoBody &G)
 
 // One thread per (cell, neighbour): the cells are those of the moving
 // bodies' boxes around their old positions (table cur), grown by one cell so
-// that they contain the boxes around the new positions (table nxt).
-// Fused body update: every block advances the bodies itself (the same
-// values everywhere) into gb; block 0 publishes the new table and clears the
-// accumulator set of the step after next.
-__device__ __forceinline__ void update_bodies_in_block(const StepArgs &a, const DevBody *__restrict__ cur,
-                                                       DevBody *__restrict__ nxt, int nbody,
-                                                       const unsigned long long *__restrict__ acc_read,
-                                                       unsigned long long *__restrict__ acc_clear, double sigma,
-                                                       double eps, int *__restrict__ err, GeoBody *gb, int blk)
-{
-    long long (*s_q)[NACC] = reinterpret_cast<long long (*)[NACC]>(gb + nbody);
-    gather_sums(nbody, acc_read, s_q);
-    for (int b = threadIdx.x; b < nbody; b += BLOCK) {
-        DevBody D;
-        advance_body(a.box, cur, nbody, b, s_q[b], a.rho0d, sigma, eps, D, err);
-        stage_geo(D, gb[b]);
-        if (blk == 0) nxt[b] = D;
-    }
-    if (blk == 0) clear_set(nbody, acc_clear);
-}
-
+// that they contain the boxes around the new positions (table nxt, written
+// by the body update of the fluid launch or by k_body).
 template <class S>
 __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *__restrict__ cur,
-                                              DevBody *__restrict__ nxt, int nbody, bool fused,
-                                              const unsigned long long *__restrict__ acc_read,
-                                              unsigned long long *__restrict__ acc_clear, double sigma, double eps,
+                                              const DevBody *__restrict__ nxt, int nbody,
                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
                                               unsigned long long *__restrict__ acc_conv,
                                               gptr<const uint8_t> own_old, gptr<uint8_t> own_new,
                                               gptr<typename S::T> A, bool after_even, gptr<float> dens,
                                               int *__restrict__ err, int blk)
 {
-    extern __shared__ double lds_dyn[];  // nbody GeoBody, then (fused) nbody x NACC sums
+    extern __shared__ double lds_dyn[];  // nbody GeoBody
     GeoBody *gb = reinterpret_cast<GeoBody *>(lds_dyn);
     __shared__ uint8_t s_on[CPB][Q + 1], s_oo[CPB][Q + 1];
     __shared__ double s_rho[CPB][Q + 1];
-    if (nlist == 0) {
-        // no moving body: the single block only updates the bodies
-        if (fused) update_bodies_in_block(a, cur, nxt, nbody, acc_read, acc_clear, sigma, eps, err, gb, blk);
-        return;
-    }
+    if (nlist == 0) return;
     const Box &bx = a.box;
     const Slot sl = slot_of(bx, cur, ids, start, nlist, 1, blk);
     const int i = sl.i;
@@ -900,14 +930,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
               nzc = wrap_small(sl.z + rcz(i), bx.nz);
     const uint32_t ncell = cell_of(bx, nxc, nyc, nzc);
     const uint8_t oo = mine ? own_old[ncell] : uint8_t(0);
-    // fused: every block advances the bodies itself (same values
-    // everywhere), block 0 publishes the new table and clears the set of the
-    // step after next; otherwise the new table is already in nxt
-    if (fused) {
-        update_bodies_in_block(a, cur, nxt, nbody, acc_read, acc_clear, sigma, eps, err, gb, blk);
-    } else {
-        for (int b = threadIdx.x; b < nbody; b += BLOCK) stage_geo(nxt[b], gb[b]);
-    }
+    for (int b = threadIdx.x; b < nbody; b += BLOCK) stage_geo(nxt[b], gb[b]);
     __syncthreads();
     bool clash = false;
     if (mine) {
@@ -1024,8 +1047,7 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D
     const int64_t t = d.t0 + k;
     if (t >= d.t_end) return;
     const int c = int(t & 1);
-    geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.nbody <= FUSE_MAX, acc_set(d.acc, t),
-                     acc_set(d.acc, t + 2), d.wca_sigma, d.wca_eps, d.mov_ids, d.mov_start, d.nmov,
+    geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.mov_ids, d.mov_start, d.nmov,
                      acc_set(d.acc, t + 1), as_global(static_cast<const uint8_t *>(d.own[c])), as_global(d.own[c ^ 1]),
                      as_global(static_cast<typename S::T *>(d.f)), c == 0, as_global(d.dens[c]), d.err,
                      int(blockIdx.x - m.geo0[si]));
@@ -1250,9 +1272,7 @@ static hipError_t launch_batch_t(const BatchLaunch &L)
         LB_TRY(hipGetLastError());
     }
     if (ng > 0) {
-        // staged bodies, plus the sums of a fused body update (at most FUSE_MAX bodies)
-        const size_t lds = size_t(L.nbody_max) * sizeof(GeoBody) +
-                           size_t(L.nbody_max < FUSE_MAX ? L.nbody_max : FUSE_MAX) * NACC * sizeof(long long);
+        const size_t lds = size_t(L.nbody_max) * sizeof(GeoBody);  // staged bodies
         hipLaunchKernelGGL(k_geoconv<S>, dim3(ng), dim3(BLOCK), lds, L.stream, L.desc, m, L.k);
         LB_TRY(hipGetLastError());
     }

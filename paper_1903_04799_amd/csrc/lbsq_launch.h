@@ -41,6 +41,7 @@ struct SimDesc {
     const int4 *blkinfo;              // per boundary block: body, first shell cell, cells, list position
     double *audit_part;
     int *err;
+    unsigned int *arrive;  // arrival counter of the boundary blocks, zero between launches
     double wca_sigma, wca_eps;
     int64_t t0, t_end;
     int nbody, nmov;
@@ -56,8 +57,10 @@ struct BatchMap {
     uint32_t geo0[MAXSIM + 1];
 };
 
-// One step of a batch: the fluid launch, then (one simulation only) the
-// audit reduction and the one-block body update, then the geometry launch.
+// One step of a batch: the fluid launch (which also updates the bodies of
+// simulations with at most FUSE_MAX bodies), then (one simulation only) the
+// audit reduction and the one-block body update for more bodies, then the
+// geometry launch.
 struct BatchLaunch {
     const SimDesc *desc;  // device array of map.nsim descriptors
     BatchMap map;
@@ -73,14 +76,12 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 
-// Geometry blocks of a simulation: none without bodies; with at most
-// FUSE_MAX bodies at least one (it carries the body update); else those of
-// the moving bodies' boxes.
+// Geometry blocks of a simulation: those of the moving bodies' boxes (the
+// body update itself runs in the fluid launch, or in k_body for more than
+// FUSE_MAX bodies).
 inline int geo_blocks(int nbody, int nblk_mov)
 {
-    if (nbody == 0) return 0;
-    if (nbody <= FUSE_MAX) return nblk_mov > 0 ? nblk_mov : 1;
-    return nblk_mov;
+    return nbody == 0 ? 0 : nblk_mov;
 }
 
 hipError_t launch_batch_step(int storage, const BatchLaunch &L);
