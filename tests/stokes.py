@@ -72,3 +72,38 @@ def steady_drag(step, get_f, set_f, fields, force_x, R, L, g, nu, rho0=1.0, iter
     u_sup = float(u[0][fluid].sum()) / float(L) ** 3
     eta = rho0 * nu
     return 6.0 * math.pi * eta * R * u_sup / F, F / (g * n_fluid)
+
+
+def squirmer_field(d, e, R, B1, B2):
+    """Flow of a squirmer in unbounded fluid (Blake 1971; Ishikawa et al.
+    2006), the paper's eq. (squirmerflow): lab-frame velocity at the offsets
+    d[3][M] from the centre, for orientation e.  It vanishes at infinity and
+    equals slip + (2/3) B1 e on r = R."""
+    r = np.sqrt((d * d).sum(axis=0))
+    n = d / r
+    en = (e[:, None] * n).sum(axis=0)
+    q3, q2, q4 = (R / r) ** 3, (R / r) ** 2, (R / r) ** 4
+    u = B1 * q3 * (en * n - e[:, None] / 3.0)
+    u += B2 * (q4 - q2) * (1.5 * en * en - 0.5) * n
+    u += B2 * q4 * en * (en * n - e[:, None])
+    return u
+
+
+def periodic_squirmer_field(x, centre, e, R, B1, B2, L, shells):
+    """eq. (squirmerflow) summed over the periodic images n L with |n| <= shells
+    (a spherical shell of images).  The sums of the r^-2 and r^-3 terms
+    converge only conditionally: the spherical order fixes them up to a
+    uniform velocity, which a comparison removes."""
+    x = np.asarray(x, dtype=float)
+    c = np.asarray(centre, dtype=float)[:, None]
+    e = np.asarray(e, dtype=float)
+    u = np.zeros_like(x)
+    rng = range(-shells, shells + 1)
+    for i in rng:
+        for j in rng:
+            for k in rng:
+                if i * i + j * j + k * k > shells * shells:
+                    continue
+                shift = np.array([i, j, k], dtype=float)[:, None] * L
+                u += squirmer_field(x - c - shift, e, R, B1, B2)
+    return u
