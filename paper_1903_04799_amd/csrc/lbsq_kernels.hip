@@ -684,15 +684,17 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     const uint32_t c = cell_of(bx, x, y, z);
     const uint32_t s = cell_of(bx, wrap_small(x - rcx(i), bx.nx), wrap_small(y - rcy(i), bx.ny),
                                wrap_small(z - rcz(i), bx.nz));
-    // the owners and both candidate populations are loaded together: the
-    // incoming population where the source is fluid, the cell's own f*_ibar
-    // (for a reflection) otherwise
+    // the owners, both candidate populations and the cell's link density
+    // are loaded together, so that no load waits for another: the incoming
+    // population where the source is fluid, the cell's own f*_ibar (for a
+    // reflection) otherwise
     const uint8_t oc = valid ? own[c] : OWN_WALL;
     const uint8_t os = (valid && i > 0) ? own[s] : OWN_FLUID;
-    float f_in = 0.0f, f_ref = 0.0f;
+    float f_in = 0.0f, f_ref = 0.0f, dprev = 0.0f;
     if (valid) {
         f_in = S::ld(F[ODD ? opp(i) * st + s : i * st + c], a.inv_scale);
         f_ref = S::ld(F[ODD ? i * st + c : opp(i) * st + s], a.inv_scale);
+        dprev = dens_prev[c];
     }
     const bool cand = oc == OWN_NB_BODY;
     const float fl = is_fluid(os) ? f_in : f_ref;
@@ -708,7 +710,7 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
         if (is_body(os)) {
             // local density of the cell's post-collision populations, kept
             // from the previous step (its slots are rewritten in place)
-            const float rw = a.rho0 + dens_prev[c];
+            const float rw = a.rho0 + dprev;
             key = os - 1;
             float fv[6];
             int kf[3], kr[3];
