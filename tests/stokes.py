@@ -107,3 +107,28 @@ def periodic_squirmer_field(x, centre, e, R, B1, B2, L, shells):
                 shift = np.array([i, j, k], dtype=float)[:, None] * L
                 u += squirmer_field(x - c - shift, e, R, B1, B2)
     return u
+
+
+def image_sum_mean_gradient(centre, e, R, B1, B2, L, shells, m=40):
+    """Box average of the velocity gradient of periodic_squirmer_field over
+    the cube of side L centred on the body: (1/V) times the surface integral
+    of u n over its faces, with an m x m midpoint rule per face.
+
+    A periodic field has zero mean gradient.  The spherical order of the image
+    sum leaves a uniform strain, proportional to the stresslet density B2 / L^3;
+    subtracting G . (x - centre) turns the sum into the periodic solution.
+    """
+    c = np.asarray(centre, dtype=float)
+    G = np.zeros((3, 3))
+    g = (np.arange(m) + 0.5) * L / m - L / 2.0
+    A, B = np.meshgrid(g, g, indexing="ij")
+    for k in range(3):
+        o = [j for j in range(3) if j != k]
+        for sign in (1.0, -1.0):
+            pts = np.zeros((3, m * m))
+            pts[o[0]] = c[o[0]] + A.ravel()
+            pts[o[1]] = c[o[1]] + B.ravel()
+            pts[k] = c[k] + sign * L / 2.0
+            u = periodic_squirmer_field(pts, c, e, R, B1, B2, L, shells)
+            G[:, k] += sign * u.mean(axis=1) / L
+    return G
