@@ -185,6 +185,33 @@ def test_prescribed_motion_geometry_bit_exact():
     check_bodies(s, o, [body], exact_pos=True)
 
 
+def test_prescribed_motion_across_periodic_boundary():
+    """Bodies whose boxes wrap around the periodic box: one starts astride a
+    corner and crosses two faces, the other crosses one.  Owners, links and
+    positions equal the oracle's bit for bit at every step."""
+    note("prescribed bodies across the periodic faces, per-step link sets")
+    shape = (28, 24, 20)
+    bodies = [dict(pos=(0.3, 23.6, 0.4), e=(0, 0, 1), R=3.2, B1=4e-3, beta=-1.5, mode="prescribed",
+                   v=(-0.11, 0.09, 0.13), w=(0.01, 0.0, -0.02)),
+              dict(pos=(22.4, 12.3, 9.7), e=(1, 0, 0), R=3.6, B1=5e-3, beta=2.5, mode="prescribed",
+                   v=(0.27, 0.21, 0.0), w=(0.0, 0.02, 0.0))]
+    o, s = make_pair(shape, bodies)
+    for t in range(30):
+        o.step(1)
+        s.step(1)
+        cg, dg, og = s.links()
+        co, do, oo = o.links()
+        assert np.array_equal(cg, co) and np.array_equal(dg, do) and np.array_equal(og, oo), t
+        for i in range(2):
+            assert np.array_equal(s.body(i)["pos"], o.body(i)["pos"]), (t, i)
+    # the first body has wrapped across the x and y faces, the second across x
+    p0, p1 = s.body(0)["pos"], s.body(1)["pos"]
+    assert p0[0] > 20.0 and p0[1] < 5.0 and p1[0] < 5.0
+    err, _ = rel_u_err(s, o)
+    assert err <= U_TOL, err
+    check_bodies(s, o, bodies, exact_pos=True)
+
+
 def test_two_squirmers_with_contact():
     """Two free squirmers swimming at each other reach WCA contact."""
     note("two squirmers, WCA")
