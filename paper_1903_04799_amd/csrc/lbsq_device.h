@@ -80,12 +80,18 @@ static_assert(lattice_tables_agree(0), "run-time D3Q19 masks disagree with the l
 
 struct StF32 {
     using T = float;
+    // waves per SIMD the fluid kernel is compiled for (its register budget;
+    // the steps with the fused audit take 4)
+    static constexpr int waves = 5;
     static __device__ __forceinline__ float ld(T v, float) { return v; }
     static __device__ __forceinline__ T st(float v, float) { return v; }
 };
 
 struct StF16 {
     using T = _Float16;
+    // waves per SIMD the fluid kernel is compiled for: half-width elements
+    // move half the bytes per load, so more waves keep enough in flight
+    static constexpr int waves = 6;
     static __device__ __forceinline__ float ld(T v, float inv) { return static_cast<float>(v) * inv; }
     // float -> half conversion rounds to nearest even
     static __device__ __forceinline__ T st(float v, float scale) { return static_cast<_Float16>(v * scale); }
@@ -93,6 +99,7 @@ struct StF16 {
 
 struct StBF16 {
     using T = uint16_t;
+    static constexpr int waves = 6;
     static __device__ __forceinline__ float ld(T v, float inv)
     {
         return __uint_as_float(static_cast<uint32_t>(v) << 16) * inv;

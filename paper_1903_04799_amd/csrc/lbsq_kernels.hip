@@ -820,7 +820,7 @@ __device__ __forceinline__ void arrive_and_update(const SimDesc &d, int c, int64
 // cells, BLOCK consecutive cells per block.  Audit partials: streaming block
 // j writes slot j, boundary block j writes slot nblk_s + j.
 template <class S, bool AUDIT, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void k_fluid(const SimDesc *__restrict__ D, BatchMap m, int64_t k)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AUDIT ? 4 : S::waves))) void k_fluid(const SimDesc *__restrict__ D, BatchMap m, int64_t k)
 {
     using T = typename S::T;
     const int si = find_sim(m.fluid0, m.nsim, blockIdx.x);
