@@ -212,6 +212,33 @@ def test_prescribed_motion_across_periodic_boundary():
     check_bodies(s, o, bodies, exact_pos=True)
 
 
+def test_more_bodies_than_the_fused_update_takes():
+    """Ten bodies (free, fixed and prescribed): more than the fluid launch's
+    last boundary block updates, so the one-block body kernel runs.  Fields,
+    owners, forces and positions against the oracle."""
+    note("ten bodies, separate body-update kernel")
+    shape = (40, 40, 24)
+    rng = np.random.default_rng(11)
+    bodies = []
+    for k in range(10):
+        e = rng.standard_normal(3)
+        mode = "fixed" if k % 4 == 3 else ("prescribed" if k == 5 else "free")
+        b = dict(pos=(6.5 + 9.0 * (k % 4) + 0.3 * rng.random(), 7.0 + 13.0 * (k // 4) + 0.3 * rng.random(),
+                      12.0 + 0.4 * rng.random()),
+                 e=tuple(e / np.linalg.norm(e)), R=2.6 + 0.6 * rng.random(), B1=0.01, beta=float(rng.uniform(-3, 3)),
+                 mode=mode)
+        if mode == "prescribed":
+            b.update(v=(0.0, 0.03, 0.05), w=(0.0, 0.0, 0.01))
+        bodies.append(b)
+    o, s = make_pair(shape, bodies)
+    for _ in range(4):
+        o.step(15)
+        s.step(15)
+        err, _ = rel_u_err(s, o)
+        assert err <= U_TOL, err
+        check_bodies(s, o, bodies)
+
+
 def test_two_squirmers_with_contact():
     """Two free squirmers swimming at each other reach WCA contact."""
     note("two squirmers, WCA")
