@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="skip the 256^3 run whose working set exceeds the last-level cache")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -264,6 +266,17 @@ def main():
                                "kernel_gbs": round(f16["kernel_gbs"], 1), "bytes_per_update": 76,
                                "traffic": measured_traffic("f16", shape, args.R),
                                "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3)}
+    if not args.no_hbm:
+        # the same kernel where the in-place working set (1.28 GB) cannot
+        # stay in the 256 MB last-level cache: the HBM-bound figure
+        n2 = (256, 256, 256)
+        h = run_gpu("f32", n2, 16.0, args.beta, 200, 50)
+        ws = 19 * (((256 ** 3 + 255) // 256) * 256 + 256) * 4
+        out["hbm_bound"] = {"workload": "free squirmer R = 16 in a periodic 256^3 box", "mlups": round(h["mlups"], 1),
+                            "ms_per_step": round(h["ms_per_step"], 5), "kernel_us": round(h["kernel_us"], 2),
+                            "achieved_gbs": round(h["kernel_gbs"], 1),
+                            "frac": round(h["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                            "working_set_mb": round(ws / 1e6, 1)}
     if not args.no_serve:
         out["served"] = run_served(args.serve_requests, args.serve_seed, args.serve_chunk, args.serve_active,
                                    args.serve_budget_gb, ["f32"] if args.no_fp16 else ["f32", "f16"])
