@@ -218,7 +218,7 @@ def main():
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-seed", type=int, default=0)
-    ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--serve-chunk", type=int, default=200)
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
