@@ -289,3 +289,40 @@ def test_E5_neutral_squirmer_oscillates_in_a_tube():
     assert abs(xmax / abs(y0) - 1.0) < 0.02
     assert ex_at_start > 0.0 and ex_end < 0.0
     assert 0.2 * travel < z_at_xmax < 0.8 * travel
+
+
+def _stripe_amplitude(s, L):
+    """Mean alternating part of u_x / v0 along the swimming axis through the
+    body: |u_i - (u_{i-1} + u_{i+1}) / 2| over runs of three fluid cells."""
+    _, u, own = s.fields()
+    b = s.body(0)
+    y, z = int(b["pos"][1]), int(b["pos"][2])
+    line = u[0, z, y, :] / V0
+    fl = own[z, y, :] == 0
+    alt = [abs(line[i] - 0.5 * (line[i - 1] + line[i + 1])) for i in range(1, L - 1)
+           if fl[i - 1] and fl[i] and fl[i + 1]]
+    return float(np.mean(alt))
+
+
+@pytest.mark.parametrize("R", [4.0, 8.0])
+def test_stripe_pattern_grows_only_at_low_resolution(R):
+    """Sec. "Squirmers in Bulk": below R of about 6 an alternating pattern of
+    fast and slow cells along the swimming direction grows with time until
+    the run becomes unstable.  At R = 4 (L = 10R) its amplitude on the axis
+    grows more than tenfold between 10,000 and 50,000 steps.  At R = 8 it
+    stays below 1% of v0 and does not grow."""
+    lbsq = gpu()
+    L = int(10 * R)
+    note("stripes: R=%g L=%d" % (R, L))
+    s = lbsq.Sim((L, L, L))
+    s.add_squirmer((L / 2.0, L / 2.0, L / 2.0), (1.0, 0.0, 0.0), R, B1=B1)
+    s.step(10000)
+    a0 = _stripe_amplitude(s, L)
+    s.step(40000)
+    a1 = _stripe_amplitude(s, L)
+    s.close()
+    note("R=%g: alternating amplitude %.4f -> %.4f v0" % (R, a0, a1))
+    if R < 6.0:
+        assert a1 > 10.0 * a0
+    else:
+        assert a1 < 0.01 and a1 < 2.0 * a0
