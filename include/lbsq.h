@@ -200,10 +200,14 @@ int lb_state_size(lb_sim *s, size_t *bytes);
 int lb_save_state(lb_sim *s, void *buf, size_t bytes);
 int lb_load_state(lb_sim *s, const void *buf, size_t bytes);
 
-/* Kernel timing for measurement: when enabled, HIP events bracket every
- * launch of the fluid-update kernel (streaming, bounce-back and collision of
- * every fluid cell); lb_kernel_time returns the summed duration (ms) and
- * launch count since it was enabled.                                      */
+/* Kernel timing for measurement: when enabled, every launch of the
+ * fluid-update kernel (streaming, bounce-back and collision of every fluid
+ * cell) made by lb_step carries a pair of HIP events that the launch stamps
+ * with its own start and end; lb_kernel_time returns the summed duration
+ * (ms) and launch count since it was enabled.  Timing changes no result;
+ * the events cost host time per step, so time the steps themselves in a
+ * separate pass.  lb_kernel_time returns LB_EDEVICE (and drops the
+ * pending events) if an elapsed time cannot be read.                      */
 int lb_kernel_timing(lb_sim *s, int enable);
 int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches);
 

@@ -841,15 +841,20 @@ int lb_kernel_time(lb_sim *s, double *ms, int64_t *launches)
     if (!s || !ms || !launches) return LB_EINVAL;
     const int st = sync_check(s);
     if (st != LB_OK) return st;
+    int rc = LB_OK;
     for (auto &e : s->evs) {
         float t = 0.0f;
-        if (hipEventElapsedTime(&t, e.first, e.second) != hipSuccess) return LB_EDEVICE;
-        s->ms += t;
-        s->launches++;
+        if (rc == LB_OK && hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) {
+            s->ms += t;
+            s->launches++;
+        } else {
+            rc = LB_EDEVICE;
+        }
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
     s->evs.clear();
+    if (rc != LB_OK) return rc;
     *ms = s->ms;
     *launches = s->launches;
     return LB_OK;

@@ -32,6 +32,8 @@
 #include "lbsq_device.h"
 #include "lbsq_launch.h"
 
+#include <hip/hip_ext.h>
+
 namespace lbsq {
 
 // ---------------------------------------------------------------------------
@@ -1255,15 +1257,21 @@ static hipError_t launch_batch_t(const BatchLaunch &L)
 {
     const BatchMap &m = L.map;
     const uint32_t nf = m.fluid0[m.nsim], ng = m.geo0[m.nsim];
-    if (L.ev_start) LB_TRY(hipEventRecord(L.ev_start, L.stream));
     if (nf > 0) {
         auto kf = L.audit ? (L.force ? k_fluid<S, true, true> : k_fluid<S, true, false>)
                           : (L.force ? k_fluid<S, false, true> : k_fluid<S, false, false>);
-        hipLaunchKernelGGL(kf, dim3(nf), dim3(BLOCK), size_t(L.nbody_max) * sizeof(LinkBody), L.stream, L.desc, m,
-                           L.k);
+        const uint32_t lds = uint32_t(size_t(L.nbody_max) * sizeof(LinkBody));
+        // timing events, when asked for, are stamped with the launch's own
+        // start and end (not with markers queued around it)
+        if (L.ev_start && L.ev_stop)
+            hipExtLaunchKernelGGL(kf, dim3(nf), dim3(BLOCK), lds, L.stream, L.ev_start, L.ev_stop, 0u, L.desc, m, L.k);
+        else
+            hipLaunchKernelGGL(kf, dim3(nf), dim3(BLOCK), lds, L.stream, L.desc, m, L.k);
         LB_TRY(hipGetLastError());
+    } else if (L.ev_start && L.ev_stop) {
+        LB_TRY(hipEventRecord(L.ev_start, L.stream));
+        LB_TRY(hipEventRecord(L.ev_stop, L.stream));
     }
-    if (L.ev_stop) LB_TRY(hipEventRecord(L.ev_stop, L.stream));
     if (L.audit) {
         hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, L.stream, L.audit_part, L.npart, L.audit_out,
                            L.err);

@@ -536,3 +536,33 @@ def test_storage_rounds_to_nearest_even(storage):
         q = (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
     want = w[:, None, None, None] + q
     assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+def test_kernel_timing_changes_no_result():
+    """Per-launch timing events (stamped by the fluid launch itself) return
+    one positive duration per step and leave every population, owner and body
+    state bit-identical to an untimed run of the same steps."""
+    L = gpu()
+    note("kernel timing: 48^3, R = 6 free squirmer, 12 steps timed and untimed")
+    out = []
+    for timed in (False, True):
+        s = L.Sim((48, 48, 48))
+        s.add_squirmer((24.3, 23.8, 24.1), (1.0, 0.2, -0.1), 6.0, B1=1e-3, beta=2.0)
+        s.step(3)
+        if timed:
+            s.kernel_timing(True)
+        s.step(12)
+        if timed:
+            ms, launches = s.kernel_time()
+            s.kernel_timing(False)
+            assert launches == 12
+            assert ms > 0.0 and ms / launches < 50.0
+        f = s.populations()
+        _, _, own = s.fields()
+        b = s.body(0)
+        s.close()
+        out.append((f, own, b))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    for k in ("pos", "e", "v", "w"):
+        assert np.array_equal(out[0][2][k], out[1][2][k])
