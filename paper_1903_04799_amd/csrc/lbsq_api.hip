@@ -385,6 +385,21 @@ int lb_create(const lb_params *p, lb_sim **out)
     for (int k = 0; k < 3; ++k) s->args.g[k] = float(p->g[k]);
     s->args.scale = std::ldexp(1.0f, p->scale_log2);
     s->args.inv_scale = std::ldexp(1.0f, -p->scale_log2);
+    {
+        // bulk collision constants (FP32 stores unscaled deviations)
+        const double sc = p->storage == LB_STORAGE_F32 ? 1.0 : std::ldexp(1.0, p->scale_log2);
+        const double wk[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+        for (int k = 0; k < 3; ++k) {
+            s->args.c_lew[k] = float(le * wk[k]);
+            s->args.c_lews[k] = float(le * wk[k] * sc);
+            s->args.c_low3s[k] = float(3.0 * lo * wk[k] * sc);
+        }
+        s->args.c_k1 = float(0.5 * (1.0 - le));
+        s->args.c_k2 = float(0.5 * (1.0 - lo));
+        s->args.c_1mle = float(1.0 - le);
+        s->args.c_s = float(sc);
+        s->args.c_is = float(1.0 / sc);
+    }
     s->esize = p->storage == LB_STORAGE_F32 ? 4 : 2;
 
     const size_t fbytes = size_t(Q) * bx.stride * s->esize;

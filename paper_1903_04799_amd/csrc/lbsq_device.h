@@ -83,6 +83,10 @@ struct StF32 {
     // waves per SIMD the fluid kernel is compiled for (its register budget;
     // the steps with the fused audit take 4)
     static constexpr int waves = 5;
+    // stored values are the deviations themselves (no scale)
+    static constexpr bool scaled = false;
+    static __device__ __forceinline__ float dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(float v) { return v; }
     static __device__ __forceinline__ float ld(T v, float) { return v; }
     static __device__ __forceinline__ T st(float v, float) { return v; }
 };
@@ -92,26 +96,30 @@ struct StF16 {
     // waves per SIMD the fluid kernel is compiled for: half-width elements
     // move half the bytes per load, so more waves keep enough in flight
     static constexpr int waves = 6;
-    static __device__ __forceinline__ float ld(T v, float inv) { return static_cast<float>(v) * inv; }
+    // stored values are the deviations times the scale 2^k
+    static constexpr bool scaled = true;
+    static __device__ __forceinline__ float dec(T v) { return static_cast<float>(v); }
     // float -> half conversion rounds to nearest even
-    static __device__ __forceinline__ T st(float v, float scale) { return static_cast<_Float16>(v * scale); }
+    static __device__ __forceinline__ T enc(float v) { return static_cast<_Float16>(v); }
+    static __device__ __forceinline__ float ld(T v, float inv) { return dec(v) * inv; }
+    static __device__ __forceinline__ T st(float v, float scale) { return enc(v * scale); }
 };
 
 struct StBF16 {
     using T = uint16_t;
     static constexpr int waves = 6;
-    static __device__ __forceinline__ float ld(T v, float inv)
-    {
-        return __uint_as_float(static_cast<uint32_t>(v) << 16) * inv;
-    }
+    static constexpr bool scaled = true;
+    static __device__ __forceinline__ float dec(T v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
     // round to nearest even on the upper 16 bits; NaN stays NaN
-    static __device__ __forceinline__ T st(float v, float scale)
+    static __device__ __forceinline__ T enc(float v)
     {
-        uint32_t u = __float_as_uint(v * scale);
+        uint32_t u = __float_as_uint(v);
         if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<T>((u >> 16) | 0x40u);
         u += 0x7fffu + ((u >> 16) & 1u);
         return static_cast<T>(u >> 16);
     }
+    static __device__ __forceinline__ float ld(T v, float inv) { return dec(v) * inv; }
+    static __device__ __forceinline__ T st(float v, float scale) { return enc(v * scale); }
 };
 
 // ---------------------------------------------------------------------------

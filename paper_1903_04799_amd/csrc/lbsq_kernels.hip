@@ -158,43 +158,68 @@ struct Nbr {
     }
 };
 
-// TRT collision of the incoming deviations f into out.
-template <bool FORCE>
+// TRT collision of the incoming deviations f into out, both as stored (times
+// the storage scale s, which is 1 in FP32).  Per pair (i, ibar) the
+// symmetric part relaxes with lam_e towards w_i (drho + rho (4.5 (c_i.u)^2 -
+// 1.5 u^2)) and the antisymmetric part with lam_o towards 3 w_i rho c_i.u.
+// Written with the pair sum sp = f_i + f_ibar and difference dm = f_i -
+// f_ibar, which also give the moments:
+//   out_i    = (1 - lam_e)/2 sp + s lam_e eq+ + (1 - lam_o)/2 dm + s lam_o eq-
+//   out_ibar = (1 - lam_e)/2 sp + s lam_e eq+ - (1 - lam_o)/2 dm - s lam_o eq-
+// with the products of lam, w_i and s taken once per simulation.
+template <class S, bool FORCE>
 __device__ __forceinline__ void collide(const StepArgs &a, const float (&f)[Q], float (&out)[Q])
 {
-    float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += f[i];
-        if (cx(i)) jx += cx(i) * f[i];
-        if (cy(i)) jy += cy(i) * f[i];
-        if (cz(i)) jz += cz(i) * f[i];
-    }
-    if (FORCE) {
-        jx += 0.5f * a.g[0];
-        jy += 0.5f * a.g[1];
-        jz += 0.5f * a.g[2];
-    }
-    const float rho = a.rho0 + drho;
-    const float ir = 1.0f / rho;
-    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    const float usq = ux * ux + uy * uy + uz * uz;
-    const float le = a.lam_e, lo = a.lam_o;
-    out[0] = f[0] - le * (f[0] - wgtf(0) * (drho - 1.5f * rho * usq));
+    float sp[Q], dm[Q];  // indexed by the odd member of each pair
+    float drs = f[0], jxs = 0.0f, jys = 0.0f, jzs = 0.0f;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
-        const int ib = i + 1;
+        sp[i] = f[i] + f[i + 1];
+        dm[i] = f[i] - f[i + 1];
+        drs += sp[i];
+        if (cx(i)) jxs += cx(i) * dm[i];
+        if (cy(i)) jys += cy(i) * dm[i];
+        if (cz(i)) jzs += cz(i) * dm[i];
+    }
+    const float drho = S::scaled ? drs * a.c_is : drs;
+    const float rho = a.rho0 + drho;
+    // one reciprocal (within 1 ulp) instead of a correctly rounded division
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    float ux, uy, uz;
+    if (FORCE) {
+        const float is = S::scaled ? a.c_is : 1.0f;
+        ux = fmaf(jxs, is, 0.5f * a.g[0]) * ir;
+        uy = fmaf(jys, is, 0.5f * a.g[1]) * ir;
+        uz = fmaf(jzs, is, 0.5f * a.g[2]) * ir;
+    } else {
+        const float q = S::scaled ? a.c_is * ir : ir;
+        ux = jxs * q;
+        uy = jys * q;
+        uz = jzs * q;
+    }
+    const float h = 1.5f * (ux * ux + uy * uy + uz * uz);
+    // s lam_e w_k (drho + rho X) = A_k + B_k X;  s lam_o 3 w_k rho c.u = C_k c.u
+    const float A0 = a.c_lew[0] * drs, A1 = a.c_lew[1] * drs, A2 = a.c_lew[2] * drs;
+    const float B0 = a.c_lews[0] * rho, B1 = a.c_lews[1] * rho, B2 = a.c_lews[2] * rho;
+    const float C1 = a.c_low3s[1] * rho, C2 = a.c_low3s[2] * rho;
+    out[0] = fmaf(a.c_1mle, f[0], fmaf(-B0, h, A0));
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const bool axis = i <= 6;
         const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        const float ep = wgtf(i) * (drho + rho * (4.5f * cu * cu - 1.5f * usq));
-        const float em = wgtf(i) * rho * 3.0f * cu;
-        const float fp = 0.5f * (f[i] + f[ib]), fm = 0.5f * (f[i] - f[ib]);
-        const float de = le * (fp - ep), dodd = lo * (fm - em);
-        out[i] = f[i] - de - dodd;
-        out[ib] = f[ib] - de + dodd;
+        const float X = fmaf(4.5f * cu, cu, -h);
+        const float ep = fmaf(axis ? B1 : B2, X, axis ? A1 : A2);
+        const float em = (axis ? C1 : C2) * cu;
+        const float P = fmaf(a.c_k1, sp[i], ep);
+        const float M = fmaf(a.c_k2, dm[i], em);
+        out[i] = P + M;
+        out[i + 1] = P - M;
     }
     if (FORCE) {
+        // Guo forcing, times s like the populations
+        const float sc = S::scaled ? a.c_s : 1.0f;
         const float ug = ux * a.g[0] + uy * a.g[1] + uz * a.g[2];
-        const float ce = 1.0f - 0.5f * le, co = 1.0f - 0.5f * lo;
+        const float ce = (1.0f - 0.5f * a.lam_e) * sc, co = (1.0f - 0.5f * a.lam_o) * sc;
         out[0] += ce * wgtf(0) * (-3.0f * ug);
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
@@ -208,13 +233,14 @@ __device__ __forceinline__ void collide(const StepArgs &a, const float (&f)[Q], 
     }
 }
 
-// The audit adds what is stored (as it will be read back).
+// The audit adds what is stored (as it will be read back); out is in the
+// stored form (times the storage scale).
 template <class S>
 __device__ __forceinline__ void audit_add(const StepArgs &a, const float (&out)[Q], double (&am)[5])
 {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double v = S::ld(S::st(out[i], a.scale), a.inv_scale);
+        const double v = S::scaled ? double(S::dec(S::enc(out[i])) * a.c_is) : double(out[i]);
         am[0] += v;
         am[1] += cx(i) * v;
         am[2] += cy(i) * v;
@@ -292,18 +318,19 @@ __device__ __forceinline__ float collide_one(const StepArgs &a, const float *f, 
 
 // Element idx of a population plane P, addressed by a 32-bit byte offset from
 // the plane's (uniform) base: the loads and stores then take the scalar-base,
-// vector-offset form.  Planes are below 4 GiB (checked at creation).
+// vector-offset form.  Planes are below 4 GiB (checked at creation).  Values
+// are in the stored form (times the storage scale).
 template <class S>
-__device__ __forceinline__ float ld_plane(gptr<const typename S::T> P, uint32_t idx, float inv)
+__device__ __forceinline__ float ld_plane(gptr<const typename S::T> P, uint32_t idx)
 {
     using T = typename S::T;
-    return S::ld(*(gptr<const T>)((gptr<const char>)P + idx * uint32_t(sizeof(T))), inv);
+    return S::dec(*(gptr<const T>)((gptr<const char>)P + idx * uint32_t(sizeof(T))));
 }
 template <class S>
-__device__ __forceinline__ void st_plane_nt(gptr<typename S::T> P, uint32_t idx, float v, float scale)
+__device__ __forceinline__ void st_plane_nt(gptr<typename S::T> P, uint32_t idx, float v)
 {
     using T = typename S::T;
-    __builtin_nontemporal_store(S::st(v, scale), (gptr<T>)((gptr<char>)P + idx * uint32_t(sizeof(T))));
+    __builtin_nontemporal_store(S::enc(v), (gptr<T>)((gptr<char>)P + idx * uint32_t(sizeof(T))));
 }
 
 // The Q plane bases of the buffer, computed in uniform control flow and
@@ -349,8 +376,8 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
         if (o == OWN_FLUID) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if (ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i), a.inv_scale);
-                else f[i] = ld_plane<S>(P.p[i], idx, a.inv_scale);
+                if (ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i));
+                else f[i] = ld_plane<S>(P.p[i], idx);
             }
         } else {
             // no-slip walls: a population that would come from a wall is the
@@ -358,16 +385,16 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const uint32_t s = nb.src(i);
-                if (ODD == is_fluid(own[s])) f[i] = ld_plane<S>(P.p[opp(i)], s, a.inv_scale);
-                else f[i] = ld_plane<S>(P.p[i], idx, a.inv_scale);
+                if (ODD == is_fluid(own[s])) f[i] = ld_plane<S>(P.p[opp(i)], s);
+                else f[i] = ld_plane<S>(P.p[i], idx);
             }
         }
         float out[Q];
-        collide<FORCE>(a, f, out);
+        collide<S, FORCE>(a, f, out);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            if (ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i], a.scale);
-            else st_plane_nt<S>(P.p[opp(i)], idx, out[i], a.scale);
+            if (ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i]);
+            else st_plane_nt<S>(P.p[opp(i)], idx, out[i]);
         }
         if (AUDIT) audit_add<S>(a, out, am);
     }

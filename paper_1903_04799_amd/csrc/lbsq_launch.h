@@ -14,6 +14,16 @@ struct StepArgs {
     float g[3];
     float scale, inv_scale;  // 2^k and 2^-k of the stored deviations
     double rho0d;
+    // Constants of the bulk collision, which works on the deviations as
+    // stored: s is the storage scale (2^k in the half-width forms, 1 in FP32)
+    // and w_k the weight of the rest (k = 0), axis (1) and diagonal (2)
+    // directions.
+    float c_lew[3];     // lam_e w_k
+    float c_lews[3];    // lam_e w_k s
+    float c_low3s[3];   // 3 lam_o w_k s
+    float c_k1, c_k2;   // (1 - lam_e) / 2, (1 - lam_o) / 2
+    float c_1mle;       // 1 - lam_e
+    float c_s, c_is;    // s, 1 / s
 };
 
 // Most simulations one batched launch can take.
