@@ -56,7 +56,8 @@ enum {
     LB_EGEOM = -4,   /* overlapping bodies, body too large for the box, too fast */
     LB_ESTATE = -5,  /* call not allowed in the current state */
     LB_ENAN = -6,    /* non-finite populations detected */
-    LB_EBUDGET = -7  /* request exceeds a memory budget */
+    LB_EBUDGET = -7, /* request exceeds a memory budget */
+    LB_ECANCELED = -8 /* request cancelled (lb_server_cancel) */
 };
 
 enum { LB_STORAGE_F32 = 0, LB_STORAGE_F16 = 1, LB_STORAGE_BF16 = 2 };
@@ -311,6 +312,14 @@ int lb_server_submit(lb_server *sv, const lb_request *rq, uint64_t *ticket);
  * first block until the oldest queued chunk is done.  *active and *queued
  * (may be NULL) receive the resident and waiting request counts.          */
 int lb_server_progress(lb_server *sv, int wait, int *active, int *queued);
+
+/* Cancel a request.  A queued request ends at once; a resident one leaves
+ * the batch at once and ends when the chunks already queued with it have
+ * run (its device memory is released only then).  Either way its result
+ * carries status LB_ECANCELED and the steps it ran.  LB_EINVAL for a ticket
+ * the server never issued, LB_ESTATE for a request that has already ended
+ * or is in its final chunk (its result comes as usual).                   */
+int lb_server_cancel(lb_server *sv, uint64_t ticket);
 
 /* Move up to cap completed results to out (oldest first); *n receives how
  * many.                                                                    */

@@ -315,6 +315,7 @@ const char *lb_strerror(int code)
     case LB_ESTATE: return "call not allowed in the current state";
     case LB_ENAN: return "non-finite populations detected";
     case LB_EBUDGET: return "memory budget exceeded";
+    case LB_ECANCELED: return "request cancelled";
     default: return "unknown error";
     }
 }

@@ -144,6 +144,7 @@ struct Job {
     double t_submit = 0.0, t_admit = 0.0;
     lb_sim *sim = nullptr;
     uint64_t fluid = 0;
+    bool cancelled = false;  // left the batch early; ends as LB_ECANCELED
 };
 
 struct Chunk {
@@ -243,7 +244,7 @@ int retire_front(lb_server *sv, bool block, bool *retired)
         if (q == hipErrorNotReady) return LB_OK;
         if (q != hipSuccess) return LB_EDEVICE;
     }
-    for (Job *j : c.done) finish(sv, j, LB_OK);
+    for (Job *j : c.done) finish(sv, j, j->cancelled ? LB_ECANCELED : LB_OK);
     (void)hipEventDestroy(c.ev);
     const hipGraphExec_t used = c.exec;
     sv->inflight.pop_front();
@@ -554,6 +555,31 @@ int lb_server_progress(lb_server *sv, int wait, int *active, int *queued)
     }());
     if (queued) *queued = int(sv->queue.size());
     return st;
+}
+
+int lb_server_cancel(lb_server *sv, uint64_t ticket)
+{
+    if (!sv) return LB_EINVAL;
+    if (ticket == 0 || ticket >= sv->next_ticket) return LB_EINVAL;
+    (void)hipSetDevice(sv->device);
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+        if ((*it)->ticket != ticket) continue;
+        Job *j = *it;
+        sv->queue.erase(it);
+        finish(sv, j, LB_ECANCELED);
+        return LB_OK;
+    }
+    for (auto it = sv->active.begin(); it != sv->active.end(); ++it) {
+        if ((*it)->ticket != ticket) continue;
+        Job *j = *it;
+        sv->active.erase(it);
+        j->cancelled = true;
+        // queued chunks may still step it: it ends with the newest of them
+        if (sv->inflight.empty()) finish(sv, j, LB_ECANCELED);
+        else sv->inflight.back().done.push_back(j);
+        return LB_OK;
+    }
+    return LB_ESTATE;
 }
 
 int lb_server_results(lb_server *sv, lb_result *out, int cap, int *n)

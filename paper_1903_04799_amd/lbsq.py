@@ -19,6 +19,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "liblbsq.so"
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EGEOM, LB_ESTATE, LB_ENAN, LB_EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
+LB_ECANCELED = -8
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 MODES = {"free": 0, "fixed": 1, "prescribed": 2}
 Q = 19
@@ -29,7 +30,7 @@ EXPORTED = [
     "lb_read_populations", "lb_write_populations", "lb_audit", "lb_info", "lb_state_size",
     "lb_save_state", "lb_load_state", "lb_kernel_timing", "lb_kernel_time", "lb_destroy",
     "lb_strerror", "lb_server_create", "lb_server_submit", "lb_server_progress", "lb_server_results",
-    "lb_server_stats_get", "lb_server_clock", "lb_server_destroy",
+    "lb_server_stats_get", "lb_server_clock", "lb_server_destroy", "lb_server_cancel",
 ]
 LB_REQ_MAXBODY = 8
 LB_SERVER_MAXACTIVE = 64
@@ -137,6 +138,7 @@ def load():
         "lb_server_stats_get": [vp, C.POINTER(LbServerStats)],
         "lb_server_clock": [vp, dp],
         "lb_server_destroy": [vp],
+        "lb_server_cancel": [vp, C.c_uint64],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -420,6 +422,16 @@ class Server:
         t = C.c_uint64()
         _check(load().lb_server_submit(self.h, C.byref(rq), C.byref(t)), "lb_server_submit")
         return t.value
+
+    def cancel(self, ticket):
+        """Cancel a queued or resident request (``lb_server_cancel``).
+        Returns True if it was cancelled, False if it had already ended or is
+        in its final chunk."""
+        rc = load().lb_server_cancel(self.h, C.c_uint64(int(ticket)))
+        if rc == LB_ESTATE:
+            return False
+        _check(rc, "lb_server_cancel")
+        return True
 
     def progress(self, wait=False):
         a, q = C.c_int(), C.c_int()

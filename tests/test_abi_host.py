@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_names_every_code():
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert lbsq.strerror(code) and lbsq.strerror(code) != "unknown error"
     assert lbsq.strerror(-99) == "unknown error"
 
@@ -102,6 +102,7 @@ def test_server_null_arguments_rejected():
     assert L.lb_server_results(None, None, 0, C.byref(n)) == lbsq.LB_EINVAL
     assert L.lb_server_stats_get(None, None) == lbsq.LB_EINVAL
     assert L.lb_server_clock(None, None) == lbsq.LB_EINVAL
+    assert L.lb_server_cancel(None, 1) == lbsq.LB_EINVAL
     assert L.lb_server_destroy(None) == lbsq.LB_EINVAL
 
 

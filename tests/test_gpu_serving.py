@@ -191,3 +191,58 @@ def test_server_reports_geometry_errors():
     results, _ = run_server(lbsq, [bad, REQUESTS[4]])
     assert results[0]["status"] == lbsq.LB_EGEOM
     assert results[1]["status"] == lbsq.LB_OK
+
+
+def test_server_cancel():
+    """Cancelling a queued request ends it at once, with LB_ECANCELED and no
+    steps. Cancelling a resident one takes it out of the batch at a chunk
+    boundary; it then reports the steps it ran. The request left in the
+    batch still matches its standalone run bit for bit, and the arena is
+    empty at the end."""
+    note("server cancellation")
+    lbsq = gpu()
+    keep, other, queued = REQUESTS[0], REQUESTS[3], REQUESTS[5]
+    results = {}
+    with lbsq.Server(1 << 30, max_active=2, chunk_steps=8) as sv:
+        tk = sv.submit(keep[0], keep[1], keep[2], tag=0)
+        to = sv.submit(other[0], other[1], 200, tag=1)
+        tq = sv.submit(queued[0], queued[1], queued[2], tag=2)  # waits for a slot
+        assert sv.cancel(tq)
+        assert not sv.cancel(tq)
+        sv.progress()
+        sv.progress()
+        assert sv.cancel(to)
+        spins = 0
+        while len(results) < 3:
+            sv.progress(wait=True)
+            for r in sv.results():
+                results[r["tag"]] = r
+            spins += 1
+            assert spins < 10000, "server made no progress"
+        assert not sv.cancel(tk)
+        with pytest.raises(lbsq.LBError) as ei:
+            sv.cancel(10 ** 6)
+        assert ei.value.code == lbsq.LB_EINVAL
+        stats = sv.stats()
+    assert results[2]["status"] == lbsq.LB_ECANCELED and results[2]["steps"] == 0
+    assert results[1]["status"] == lbsq.LB_ECANCELED
+    assert 0 < results[1]["steps"] < 200 and results[1]["steps"] % 8 == 0
+    assert results[0]["status"] == lbsq.LB_OK and results[0]["steps"] == keep[2]
+    assert_same(results[0], alone(lbsq, keep[0], keep[1], keep[2]), "request kept beside cancellations")
+    assert stats["arena_in_use"] == 0
+
+
+def test_server_isolates_a_diverging_request():
+    """A request whose fluid diverges (a slip of 5 lattice units per step,
+    far beyond the lattice speed) ends with its own error, LB_ENAN or
+    LB_EGEOM. The request batched with it still matches its standalone run
+    bit for bit."""
+    note("server: diverging request beside a normal one")
+    lbsq = gpu()
+    bad = ((24, 24, 24), [dict(pos=(12.2, 11.8, 12.1), e=(1, 0, 0), R=4.0, B1=5.0, beta=0.0)], 120)
+    good = REQUESTS[0]
+    results, stats = run_server(lbsq, [bad, good], chunk=8, max_active=2)
+    assert results[0]["status"] in (lbsq.LB_ENAN, lbsq.LB_EGEOM), lbsq.strerror(results[0]["status"])
+    assert results[1]["status"] == lbsq.LB_OK
+    assert_same(results[1], alone(lbsq, good[0], good[1], good[2]), "request beside a diverging one")
+    assert stats["arena_in_use"] == 0
