@@ -127,6 +127,7 @@ typedef struct {
     uint32_t *cov_cell, *unc_cell;
     uint8_t *cov_body, *unc_body;
     int geom_error;
+    int runaway; /* a body moved a cell or more in one step: stepping stops */
 } or_sim;
 
 /* ------------------------------------------------------------------ */
@@ -383,11 +384,13 @@ int or_set_static_mask(or_sim *s, const uint8_t *solid, const double *wall_u)
     return err;
 }
 
-/* Add a body; returns its id (>= 0) or -1 on bad input, -2 on overlap. */
+/* Add a body; returns its id (>= 0) or -1 on bad input (a free body needs
+ * a positive density: its mass divides the force), -2 on overlap. */
 int or_add_body(or_sim *s, const double pos[3], const double e[3], double R, double B1,
                 double beta, int mode, const double v[3], const double w[3], double rho_p)
 {
     if (s->step != 0 || s->nbody >= OR_MAXB || R <= 0.0) return -1;
+    if (mode == OR_FREE && !(rho_p > 0.0)) return -1;
     double en = sqrt(dot(e, e));
     if (en == 0.0) return -1;
     or_body *b = &s->body[s->nbody];
@@ -715,14 +718,23 @@ static void one_step(or_sim *s)
             B->T[k] = B->Tbb[k] + B->Tc[k];
         }
         or_integrate(B->pos, B->e, B->v, B->w, B->F, B->T, B->m, B->I, B->mode, nn);
+        /* the cell conversion below compares owners one step apart, which
+           takes a body moving less than one cell per step: a faster or
+           non-finite velocity ends the run with a geometry error */
+        for (int k = 0; k < 3; ++k)
+            if (!(fabs(B->v[k]) < 1.0)) s->runaway = 1;
+    }
+    s->step++;
+    if (s->runaway) {
+        s->geom_error = 1;
+        return;
     }
     convert_cells(s);
-    s->step++;
 }
 
 int or_step(or_sim *s, int nsteps)
 {
-    for (int t = 0; t < nsteps; ++t) one_step(s);
+    for (int t = 0; t < nsteps && !s->runaway; ++t) one_step(s);
     return s->geom_error ? -2 : 0;
 }
 
