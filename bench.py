@@ -80,12 +80,15 @@ def run_gpu(storage, shape, R, beta, steps, warmup):
     sim.step(warmup)
     sim.sync()
     n_fluid = sim.info()["n_fluid"]
+    mass0 = sim.audit()[0]  # FP64 fluid mass, outside the timed region
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    mass1 = sim.audit()[0]
+    n_fluid1 = sim.info()["n_fluid"]
     # kernel-level timing of the fused stream-collide launches (HIP events
     # recorded on the simulation's own stream)
     sim.kernel_timing(True)
@@ -104,6 +107,12 @@ def run_gpu(storage, shape, R, beta, steps, warmup):
         "kernel_gbs": bytes_launch / avg_s / 1e9,
         "bytes_per_launch": bytes_launch,
         "v_over_v0": float(v[0] / (2.0 / 3.0 * 1e-3)),
+        # FP64 fluid mass over the timed steps: its relative change, the
+        # change in fluid cells as the sphere moves across the lattice, and
+        # the relative change of the mean density (mass per fluid cell)
+        "conservation": {"mass_rel_change": (mass1 - mass0) / mass0,
+                         "fluid_cells_change": int(n_fluid1) - int(n_fluid),
+                         "mean_density_rel_change": (mass1 / n_fluid1) / (mass0 / n_fluid) - 1.0},
     }
 
 
@@ -257,6 +266,7 @@ def main():
                      "algorithmic_bytes_per_launch": f32["bytes_per_launch"],
                      "kernel": "k_fluid", "kernel_us": round(f32["kernel_us"], 2),
                      "bytes_per_update": BYTES_PER_UPDATE["f32"]},
+        "conservation": f32["conservation"],
     }
     if not args.no_fp16:
         f16 = run_gpu("f16", shape, args.R, args.beta, args.steps, args.warmup)
@@ -265,7 +275,8 @@ def main():
                                "kernel_us": round(f16["kernel_us"], 2),
                                "kernel_gbs": round(f16["kernel_gbs"], 1), "bytes_per_update": 76,
                                "traffic": measured_traffic("f16", shape, args.R),
-                               "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3)}
+                               "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3),
+                               "conservation": f16["conservation"]}
     if not args.no_hbm:
         # the same kernel where the in-place working set (1.28 GB) cannot
         # stay in the 256 MB last-level cache: the HBM-bound figure
