@@ -21,13 +21,15 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
+# roctx ranges around the API's host-side phases (profiler marker trace)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> Path:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB.with_suffix(".so.tmp%d" % os.getpid())
     cmd = [hipcc, *HIPCC_FLAGS, "-I", str(ROOT / "include"), "-o", str(tmp),
-           *[str(CSRC / s) for s in SOURCES]]
+           *[str(CSRC / s) for s in SOURCES], *LINK]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

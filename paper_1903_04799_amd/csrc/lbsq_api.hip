@@ -454,6 +454,7 @@ int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n)
 int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
 {
     if (!s || !q) return LB_EINVAL;
+    const TraceRange tr("lb_add_squirmer");
     if (s->started) return LB_ESTATE;
     if (int(s->bodies.size()) >= MAXB) return LB_EINVAL;
     if (q->mode < LB_FREE || q->mode > LB_PRESCRIBED) return LB_EINVAL;
@@ -511,6 +512,7 @@ int lb_add_squirmer(lb_sim *s, const lb_squirmer *q, int *id)
 int lb_step(lb_sim *s, int nsteps)
 {
     if (!s || nsteps < 0) return LB_EINVAL;
+    const TraceRange tr("lb_step");
     (void)hipSetDevice(s->device);
     const int cl = classify_now(s);
     if (cl != LB_OK) return cl;
@@ -555,6 +557,7 @@ int lb_sync(lb_sim *s)
 int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
 {
     if (!s || !rho || !u) return LB_EINVAL;
+    const TraceRange tr("lb_read_fields");
     const int st = sync_check(s);
     if (st != LB_OK) return st;
     const uint32_t n = s->args.box.n;
@@ -727,6 +730,7 @@ static int audit_now(lb_sim *s, double out[5])
 int lb_audit(lb_sim *s, double *mass, double P[3])
 {
     if (!s || !mass || !P) return LB_EINVAL;
+    const TraceRange tr("lb_audit");
     double a[5];
     const int st = audit_now(s, a);
     if (st != LB_OK) return st;

@@ -238,6 +238,7 @@ int retire_front(lb_server *sv, bool block, bool *retired)
     if (sv->inflight.empty()) return LB_OK;
     Chunk &c = sv->inflight.front();
     if (block) {
+        const TraceRange tr("lb_server wait");
         if (hipEventSynchronize(c.ev) != hipSuccess) return LB_EDEVICE;
     } else {
         const hipError_t q = hipEventQuery(c.ev);
@@ -262,6 +263,8 @@ int retire_front(lb_server *sv, bool block, bool *retired)
 // waits for it before the next chunk.
 int admit(lb_server *sv)
 {
+    if (sv->queue.empty() || int(sv->active.size()) >= sv->p.max_active) return LB_OK;
+    const TraceRange tr("lb_server admit");
     bool any = false;
     while (!sv->queue.empty() && int(sv->active.size()) < sv->p.max_active) {
         Job *j = sv->queue.front();
@@ -324,6 +327,7 @@ int admit(lb_server *sv)
 // Enqueue one chunk of the resident requests.
 int launch_chunk(lb_server *sv)
 {
+    const TraceRange tr("lb_server chunk");
     const int n = int(sv->active.size());
     std::vector<lb_sim *> sims(n);
     int64_t kmax = 0;
@@ -419,6 +423,7 @@ int lb_step_batch(lb_sim *const *sims, int n, int nsteps)
             if (sims[j] == sims[k]) return LB_EINVAL;
     }
     if (n == 0 || nsteps == 0) return LB_OK;
+    const TraceRange tr("lb_step_batch");
     bool together = n <= MAXSIM;
     for (int k = 0; k < n && together; ++k)
         together = batchable(sims[k]) && sims[k]->p.storage == sims[0]->p.storage &&

@@ -5,8 +5,20 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/lbsq.h"
 #include "lbsq_launch.h"
+
+// A roctx range over a host-side phase of the API (stepping, set-up,
+// readout, the server's admission and chunks), visible in a profiler's
+// marker trace; without a profiler it costs a call.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 struct lb_sim {
     lb_params p;
