@@ -212,15 +212,17 @@ def test_prescribed_motion_across_periodic_boundary():
     check_bodies(s, o, bodies, exact_pos=True)
 
 
-def test_more_bodies_than_the_fused_update_takes():
-    """Ten bodies (free, fixed and prescribed): more than the fluid launch's
-    last boundary block updates, so the one-block body kernel runs.  Fields,
+@pytest.mark.parametrize("nbody", [8, 9, 10])
+def test_many_bodies_fused_and_separate_update(nbody):
+    """Free, fixed and prescribed bodies at the limit of the body update in
+    the fluid launch's last boundary block (8, its LDS tables full) and just
+    past it (9, 10: the one-block body kernel runs instead).  Fields,
     owners, forces and positions against the oracle."""
-    note("ten bodies, separate body-update kernel")
+    note("%d bodies, %s body update" % (nbody, "fused" if nbody <= 8 else "separate"))
     shape = (40, 40, 24)
     rng = np.random.default_rng(11)
     bodies = []
-    for k in range(10):
+    for k in range(nbody):
         e = rng.standard_normal(3)
         mode = "fixed" if k % 4 == 3 else ("prescribed" if k == 5 else "free")
         b = dict(pos=(6.5 + 9.0 * (k % 4) + 0.3 * rng.random(), 7.0 + 13.0 * (k // 4) + 0.3 * rng.random(),
