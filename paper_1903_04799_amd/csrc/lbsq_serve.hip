@@ -2,6 +2,9 @@
 // lb_step_batch call and the continuous-batching server (lb_server_*) of
 // include/lbsq.h.
 //
+// The server's policy (queue, admission, chunks, retirement, cancellation)
+// is lbsq_sched.h; this file gives it the HIP backend.
+//
 // Both run the step kernels over a table of simulation descriptors: each
 // step is one fluid launch and one geometry launch whose blocks are divided
 // among the simulations (contiguous ranges per simulation), so a batch costs
@@ -17,6 +20,7 @@
 #include <new>
 #include <vector>
 
+#include "lbsq_sched.h"
 #include "lbsq_sim.h"
 
 using namespace lbsq;
@@ -76,85 +80,14 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// the serving loop
+// the serving loop: the policy of lbsq_sched.h over the HIP backend below
 
 namespace {
 
-// First-fit allocator over one device allocation (256-byte granules);
-// neighbouring free ranges are merged.
-struct Arena {
-    char *base = nullptr;
-    size_t size = 0;
-    std::map<size_t, size_t> free_, used_;  // offset -> bytes
+constexpr int RING = 3;  // pinned descriptor tables (two chunks queued at most)
+static_assert(RING > SERVE_MAX_QUEUED, "a queued chunk's descriptor table must not be overwritten");
 
-    void reset(char *b, size_t n)
-    {
-        base = b;
-        size = n;
-        free_.clear();
-        used_.clear();
-        free_[0] = n;
-    }
-    void *alloc(size_t bytes)
-    {
-        bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            const size_t off = it->first, sz = it->second;
-            free_.erase(it);
-            if (sz > bytes) free_[off + bytes] = sz - bytes;
-            used_[off] = bytes;
-            return base + off;
-        }
-        return nullptr;
-    }
-    void release(void *p)
-    {
-        if (!p) return;
-        const size_t off = size_t(static_cast<char *>(p) - base);
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t sz = u->second;
-        used_.erase(u);
-        auto nx = free_.lower_bound(off);
-        if (nx != free_.end() && nx->first == off + sz) {
-            sz += nx->second;
-            nx = free_.erase(nx);
-        }
-        if (nx != free_.begin()) {
-            auto pv = std::prev(nx);
-            if (pv->first + pv->second == off) {
-                pv->second += sz;
-                return;
-            }
-        }
-        free_[off] = sz;
-    }
-    size_t in_use() const
-    {
-        size_t t = 0;
-        for (const auto &u : used_) t += u.second;
-        return t;
-    }
-};
-
-struct Job {
-    uint64_t ticket = 0;
-    lb_request rq{};
-    double t_submit = 0.0, t_admit = 0.0;
-    lb_sim *sim = nullptr;
-    uint64_t fluid = 0;
-    bool cancelled = false;  // left the batch early; ends as LB_ECANCELED
-};
-
-struct Chunk {
-    hipEvent_t ev = nullptr;
-    hipGraphExec_t exec = nullptr;  // the graph this chunk replayed, if any
-    std::vector<Job *> done;        // requests whose last step is in this chunk
-};
-
-constexpr int RING = 3;      // pinned descriptor tables (two chunks queued at most)
-constexpr int MAX_QUEUED = 2;
+struct GpuBackend;
 
 }  // namespace
 
@@ -165,19 +98,17 @@ struct lb_server {
     bool own_stream = false;
     Arena arena;
     void *arena_mem = nullptr;
-    uint64_t next_ticket = 1;
-    std::deque<Job *> queue;
-    std::vector<Job *> active;
-    std::deque<Chunk> inflight;
-    std::deque<lb_result> results;
     SimDesc *d_desc = nullptr;  // descriptors read by the chunk kernels
     SimDesc *h_desc = nullptr;  // RING pinned tables of MAXSIM descriptors
     int ring = 0;
     hipEvent_t setup_ev = nullptr;
     hipGraphExec_t exec = nullptr;  // graph of the current set of requests
     std::vector<uint32_t> exec_key;
-    lb_server_stats stats{};
+    std::map<hipGraphExec_t, int> graph_refs;  // queued chunks replaying each graph
+    uint64_t graphs = 0;
     std::chrono::steady_clock::time_point t0;
+    GpuBackend *be = nullptr;
+    ServeCore<GpuBackend> *core = nullptr;
 };
 
 namespace {
@@ -200,75 +131,31 @@ size_t request_bytes(const lb_request *rq, int storage)
     return t;
 }
 
-void finish(lb_server *sv, Job *j, int status)
-{
-    lb_result r;
-    std::memset(&r, 0, sizeof(r));
-    r.ticket = j->ticket;
-    r.tag = j->rq.tag;
-    r.nbody = j->rq.nbody;
-    r.t_submit = j->t_submit;
-    r.t_admit = j->t_admit;
-    r.fluid_cells = j->fluid;
-    if (j->sim) {
-        lb_sim *s = j->sim;
-        r.steps = s->steps;
-        for (int b = 0; b < int(s->bodies.size()) && status == LB_OK; ++b) {
-            status = lb_body_state(s, b, r.pos[b], r.e[b], r.v[b], r.w[b], nullptr);
-            if (status == LB_OK) status = lb_force_torque(s, b, r.F[b], r.T[b]);
-        }
-        if (status == LB_OK) {
-            double P[3];
-            status = lb_audit(s, &r.mass, P);
-        }
-        lb_destroy(s);
-        j->sim = nullptr;
-    }
-    r.status = status;
-    r.t_done = seconds_since(sv->t0);
-    sv->results.push_back(r);
-    sv->stats.completed++;
-    delete j;
-}
+// Simulations are lb_sim handles allocated in the server's arena; a chunk is
+// one descriptor upload plus K batched steps (a graph replay, or launches
+// one by one) and the event recorded after them.
+struct GpuBackend {
+    lb_server *sv;
+    using Sim = lb_sim *;
+    struct Token {
+        hipEvent_t ev = nullptr;
+        hipGraphExec_t exec = nullptr;  // the graph this chunk replayed, if any
+    };
 
-// Retire the oldest queued chunk if it is done (or wait for it).
-int retire_front(lb_server *sv, bool block, bool *retired)
-{
-    *retired = false;
-    if (sv->inflight.empty()) return LB_OK;
-    Chunk &c = sv->inflight.front();
-    if (block) {
-        const TraceRange tr("lb_server wait");
-        if (hipEventSynchronize(c.ev) != hipSuccess) return LB_EDEVICE;
-    } else {
-        const hipError_t q = hipEventQuery(c.ev);
-        if (q == hipErrorNotReady) return LB_OK;
-        if (q != hipSuccess) return LB_EDEVICE;
+    double now() const { return seconds_since(sv->t0); }
+    int64_t steps(Sim s) const { return s->steps; }
+    void advance(Sim s, int64_t n)
+    {
+        s->steps += n;
+        s->cur = int(s->steps & 1);
     }
-    for (Job *j : c.done) finish(sv, j, j->cancelled ? LB_ECANCELED : LB_OK);
-    (void)hipEventDestroy(c.ev);
-    const hipGraphExec_t used = c.exec;
-    sv->inflight.pop_front();
-    if (used && used != sv->exec) {
-        bool still = false;
-        for (const Chunk &o : sv->inflight) still |= o.exec == used;
-        if (!still) (void)hipGraphExecDestroy(used);
-    }
-    *retired = true;
-    return LB_OK;
-}
+    void destroy(Sim s) { lb_destroy(s); }
 
-// Admit queued requests while slots and arena memory allow (first come,
-// first served).  Set-up work runs on the set-up stream; the batch stream
-// waits for it before the next chunk.
-int admit(lb_server *sv)
-{
-    if (sv->queue.empty() || int(sv->active.size()) >= sv->p.max_active) return LB_OK;
-    const TraceRange tr("lb_server admit");
-    bool any = false;
-    while (!sv->queue.empty() && int(sv->active.size()) < sv->p.max_active) {
-        Job *j = sv->queue.front();
-        const lb_request &rq = j->rq;
+    // Set-up work runs on the set-up stream while chunks run.
+    int create(const lb_request &rq, Sim *out, uint64_t *fluid)
+    {
+        const TraceRange tr("lb_server admit");
+        *out = nullptr;
         lb_params p;
         std::memset(&p, 0, sizeof(p));
         p.nx = rq.nx;
@@ -292,123 +179,125 @@ int admit(lb_server *sv)
             rc = lb_add_squirmer(s, &rq.body[b], &id);
         }
         if (rc == LB_OK) rc = lbsq_prepare(s);
-        if (rc == LB_OK) rc = lb_info(s, &j->fluid, nullptr);
-        if (rc == LB_ENOMEM) {
-            if (s) lb_destroy(s);
-            // nothing else holds memory: it will never fit
-            if (!sv->active.empty() || !sv->inflight.empty()) break;
-            sv->queue.pop_front();
-            finish(sv, j, LB_EBUDGET);
-            continue;
-        }
-        sv->queue.pop_front();
-        j->t_admit = seconds_since(sv->t0);
+        if (rc == LB_OK) rc = lb_info(s, fluid, nullptr);
         if (rc != LB_OK) {
             if (s) lb_destroy(s);
-            finish(sv, j, rc);
-            continue;
+            return rc;
         }
-        j->sim = s;
-        if (rq.nsteps == 0) {
-            finish(sv, j, LB_OK);
-            continue;
-        }
-        sv->active.push_back(j);
-        any = true;
+        *out = s;
+        return LB_OK;
     }
-    if (any) {
+
+    // The batch stream waits for the set-up work before the next chunk.
+    int admitted()
+    {
         if (hipEventRecord(sv->setup_ev, sv->setup) != hipSuccess ||
             hipStreamWaitEvent(sv->stream, sv->setup_ev, 0) != hipSuccess)
             return LB_EDEVICE;
+        return LB_OK;
     }
-    return LB_OK;
-}
 
-// Enqueue one chunk of the resident requests.
-int launch_chunk(lb_server *sv)
-{
-    const TraceRange tr("lb_server chunk");
-    const int n = int(sv->active.size());
-    std::vector<lb_sim *> sims(n);
-    int64_t kmax = 0;
-    for (int j = 0; j < n; ++j) {
-        sims[j] = sv->active[j]->sim;
-        kmax = std::max(kmax, sv->active[j]->rq.nsteps - sims[j]->steps);
-    }
-    const Batch b = make_batch(sims.data(), n);
-    SimDesc *h = sv->h_desc + size_t(sv->ring) * MAXSIM;
-    sv->ring = (sv->ring + 1) % RING;
-    for (int j = 0; j < n; ++j) lbsq_fill_desc(sims[j], sims[j]->steps, sv->active[j]->rq.nsteps, h[j]);
-    if (hipMemcpyAsync(sv->d_desc, h, size_t(n) * sizeof(SimDesc), hipMemcpyHostToDevice, sv->stream) != hipSuccess)
-        return LB_EDEVICE;
-    Chunk c;
-    const int K = sv->p.chunk_steps;
-    if (sv->p.use_graph) {
-        // one graph per set of resident requests (their block ranges)
-        std::vector<uint32_t> key;
-        key.push_back(uint32_t(K));
-        key.push_back(uint32_t(b.nbody_max));
-        for (int j = 0; j <= n; ++j) {
-            key.push_back(b.map.fluid0[j]);
-            key.push_back(b.map.geo0[j]);
+    int launch(const std::vector<Sim> &sims, const std::vector<int64_t> &ends, int K, Token *tok)
+    {
+        const TraceRange tr("lb_server chunk");
+        const int n = int(sims.size());
+        int64_t kmax = 0;
+        for (int j = 0; j < n; ++j) kmax = std::max(kmax, ends[j] - sims[j]->steps);
+        const Batch b = make_batch(sims.data(), n);
+        SimDesc *h = sv->h_desc + size_t(sv->ring) * MAXSIM;
+        sv->ring = (sv->ring + 1) % RING;
+        for (int j = 0; j < n; ++j) lbsq_fill_desc(sims[j], sims[j]->steps, ends[j], h[j]);
+        if (hipMemcpyAsync(sv->d_desc, h, size_t(n) * sizeof(SimDesc), hipMemcpyHostToDevice, sv->stream) !=
+            hipSuccess)
+            return LB_EDEVICE;
+        Token t;
+        if (sv->p.use_graph) {
+            // one graph per set of resident requests (their block ranges)
+            std::vector<uint32_t> key;
+            key.push_back(uint32_t(K));
+            key.push_back(uint32_t(b.nbody_max));
+            for (int j = 0; j <= n; ++j) {
+                key.push_back(b.map.fluid0[j]);
+                key.push_back(b.map.geo0[j]);
+            }
+            if (!sv->exec || key != sv->exec_key) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t e = nullptr;
+                if (hipStreamBeginCapture(sv->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return LB_EDEVICE;
+                const hipError_t le = enqueue_steps(sv->p.storage, sv->d_desc, b, K, sv->capture);
+                const hipError_t ce = hipStreamEndCapture(sv->capture, &g);
+                if (le != hipSuccess || ce != hipSuccess) return LB_EDEVICE;
+                const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) return LB_EDEVICE;
+                // the previous graph goes when no queued chunk replays it
+                if (sv->exec && sv->graph_refs.find(sv->exec) == sv->graph_refs.end())
+                    (void)hipGraphExecDestroy(sv->exec);
+                sv->exec = e;
+                sv->exec_key = key;
+                sv->graphs++;
+            }
+            if (hipGraphLaunch(sv->exec, sv->stream) != hipSuccess) return LB_EDEVICE;
+            t.exec = sv->exec;
+            sv->graph_refs[sv->exec]++;
+        } else {
+            const int kk = int(std::min<int64_t>(K, kmax));
+            if (enqueue_steps(sv->p.storage, sv->d_desc, b, kk, sv->stream) != hipSuccess) return LB_EDEVICE;
         }
-        if (!sv->exec || key != sv->exec_key) {
-            hipGraph_t g = nullptr;
-            hipGraphExec_t e = nullptr;
-            if (hipStreamBeginCapture(sv->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return LB_EDEVICE;
-            const hipError_t le = enqueue_steps(sv->p.storage, sv->d_desc, b, K, sv->capture);
-            const hipError_t ce = hipStreamEndCapture(sv->capture, &g);
-            if (le != hipSuccess || ce != hipSuccess) return LB_EDEVICE;
-            const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ie != hipSuccess) return LB_EDEVICE;
-            // the previous graph goes when no queued chunk uses it any more
-            bool still = false;
-            for (const Chunk &o : sv->inflight) still |= o.exec == sv->exec;
-            if (sv->exec && !still) (void)hipGraphExecDestroy(sv->exec);
-            sv->exec = e;
-            sv->exec_key = key;
-            sv->stats.graphs++;
+        if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(t.ev, sv->stream) != hipSuccess) {
+            // the chunk is queued but cannot be tracked: let it finish first
+            (void)hipStreamSynchronize(sv->stream);
+            release(t);
+            return LB_EDEVICE;
         }
-        if (hipGraphLaunch(sv->exec, sv->stream) != hipSuccess) return LB_EDEVICE;
-        c.exec = sv->exec;
-    } else {
-        const int kk = int(std::min<int64_t>(K, kmax));
-        if (enqueue_steps(sv->p.storage, sv->d_desc, b, kk, sv->stream) != hipSuccess) return LB_EDEVICE;
+        *tok = t;
+        return LB_OK;
     }
-    if (hipEventCreateWithFlags(&c.ev, hipEventDisableTiming) != hipSuccess) return LB_EDEVICE;
-    if (hipEventRecord(c.ev, sv->stream) != hipSuccess) {
-        (void)hipEventDestroy(c.ev);
-        return LB_EDEVICE;
-    }
-    std::vector<Job *> keep;
-    for (Job *j : sv->active) {
-        lb_sim *s = j->sim;
-        const int64_t adv = std::min<int64_t>(K, j->rq.nsteps - s->steps);
-        s->steps += adv;
-        s->cur = int(s->steps & 1);
-        sv->stats.cell_updates += j->fluid * uint64_t(adv);
-        if (s->steps == j->rq.nsteps) c.done.push_back(j);
-        else keep.push_back(j);
-    }
-    sv->active.swap(keep);
-    sv->inflight.push_back(c);
-    sv->stats.chunks++;
-    return LB_OK;
-}
 
-int pump(lb_server *sv)
-{
-    bool r = true;
-    while (r) {
-        const int st = retire_front(sv, false, &r);
-        if (st != LB_OK) return st;
+    int poll(Token &t, bool block, bool *done)
+    {
+        *done = false;
+        if (block) {
+            const TraceRange tr("lb_server wait");
+            if (hipEventSynchronize(t.ev) != hipSuccess) return LB_EDEVICE;
+        } else {
+            const hipError_t q = hipEventQuery(t.ev);
+            if (q == hipErrorNotReady) return LB_OK;
+            if (q != hipSuccess) return LB_EDEVICE;
+        }
+        *done = true;
+        return LB_OK;
     }
-    int st = admit(sv);
-    if (st != LB_OK) return st;
-    if (!sv->active.empty() && int(sv->inflight.size()) < MAX_QUEUED) return launch_chunk(sv);
-    return LB_OK;
-}
+
+    void release(Token &t)
+    {
+        if (t.ev) (void)hipEventDestroy(t.ev);
+        if (t.exec) {
+            auto it = sv->graph_refs.find(t.exec);
+            if (it != sv->graph_refs.end() && --it->second == 0) {
+                if (t.exec != sv->exec) (void)hipGraphExecDestroy(t.exec);
+                sv->graph_refs.erase(it);
+            }
+        }
+        t = Token{};
+    }
+
+    int read_result(Sim s, lb_result *r)
+    {
+        int status = LB_OK;
+        for (int b = 0; b < int(s->bodies.size()) && status == LB_OK; ++b) {
+            status = lb_body_state(s, b, r->pos[b], r->e[b], r->v[b], r->w[b], nullptr);
+            if (status == LB_OK) status = lb_force_torque(s, b, r->F[b], r->T[b]);
+        }
+        if (status == LB_OK) {
+            double P[3];
+            status = lb_audit(s, &r->mass, P);
+        }
+        return status;
+    }
+};
 
 }  // namespace
 
@@ -514,11 +403,16 @@ int lb_server_create(const lb_server_params *p, lb_server **out)
                         hipHostMalloc(&sv->h_desc, RING * MAXSIM * sizeof(SimDesc), hipHostMallocDefault) !=
                             hipSuccess))
         rc = LB_ENOMEM;
+    if (rc == LB_OK) {
+        sv->arena.reset(static_cast<char *>(sv->arena_mem), p->budget_bytes);
+        sv->be = new (std::nothrow) GpuBackend{sv};
+        if (sv->be) sv->core = new (std::nothrow) ServeCore<GpuBackend>(*sv->be, p->max_active, p->chunk_steps);
+        if (!sv->core) rc = LB_ENOMEM;
+    }
     if (rc != LB_OK) {
         lb_server_destroy(sv);
         return rc;
     }
-    sv->arena.reset(static_cast<char *>(sv->arena_mem), p->budget_bytes);
     *out = sv;
     return LB_OK;
 }
@@ -531,78 +425,37 @@ int lb_server_submit(lb_server *sv, const lb_request *rq, uint64_t *ticket)
         return LB_EINVAL;
     if (uint64_t(rq->nx) * rq->ny * rq->nz >= (uint64_t(1) << 32)) return LB_EINVAL;
     if (request_bytes(rq, sv->p.storage) > sv->p.budget_bytes) return LB_EBUDGET;
-    Job *j = new (std::nothrow) Job();
-    if (!j) return LB_ENOMEM;
-    j->ticket = sv->next_ticket++;
-    j->rq = *rq;
-    j->t_submit = seconds_since(sv->t0);
-    sv->queue.push_back(j);
-    if (ticket) *ticket = j->ticket;
-    return LB_OK;
+    return sv->core->submit(*rq, ticket);
+}
+
+int lb_server_cancel(lb_server *sv, uint64_t ticket)
+{
+    if (!sv) return LB_EINVAL;
+    (void)hipSetDevice(sv->device);
+    return sv->core->cancel(ticket);
 }
 
 int lb_server_progress(lb_server *sv, int wait, int *active, int *queued)
 {
     if (!sv) return LB_EINVAL;
     (void)hipSetDevice(sv->device);
-    int st = LB_OK;
-    if (wait && !sv->inflight.empty()) {
-        bool r = false;
-        st = retire_front(sv, true, &r);
-    }
-    if (st == LB_OK) st = pump(sv);
-    // keep the device fed: a second chunk behind the running one
-    if (st == LB_OK && !sv->active.empty() && int(sv->inflight.size()) < MAX_QUEUED) st = pump(sv);
-    if (active) *active = int(sv->active.size() + [&] {
-        size_t t = 0;
-        for (const Chunk &c : sv->inflight) t += c.done.size();
-        return t;
-    }());
-    if (queued) *queued = int(sv->queue.size());
-    return st;
-}
-
-int lb_server_cancel(lb_server *sv, uint64_t ticket)
-{
-    if (!sv) return LB_EINVAL;
-    if (ticket == 0 || ticket >= sv->next_ticket) return LB_EINVAL;
-    (void)hipSetDevice(sv->device);
-    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
-        if ((*it)->ticket != ticket) continue;
-        Job *j = *it;
-        sv->queue.erase(it);
-        finish(sv, j, LB_ECANCELED);
-        return LB_OK;
-    }
-    for (auto it = sv->active.begin(); it != sv->active.end(); ++it) {
-        if ((*it)->ticket != ticket) continue;
-        Job *j = *it;
-        sv->active.erase(it);
-        j->cancelled = true;
-        // queued chunks may still step it: it ends with the newest of them
-        if (sv->inflight.empty()) finish(sv, j, LB_ECANCELED);
-        else sv->inflight.back().done.push_back(j);
-        return LB_OK;
-    }
-    return LB_ESTATE;
+    return sv->core->progress(wait != 0, active, queued);
 }
 
 int lb_server_results(lb_server *sv, lb_result *out, int cap, int *n)
 {
     if (!sv || !n || cap < 0 || (!out && cap > 0)) return LB_EINVAL;
-    int k = 0;
-    while (k < cap && !sv->results.empty()) {
-        out[k++] = sv->results.front();
-        sv->results.pop_front();
-    }
-    *n = k;
-    return LB_OK;
+    return sv->core->results(out, cap, n);
 }
 
 int lb_server_stats_get(lb_server *sv, lb_server_stats *st)
 {
     if (!sv || !st) return LB_EINVAL;
-    *st = sv->stats;
+    std::memset(st, 0, sizeof(*st));
+    st->cell_updates = sv->core->cell_updates;
+    st->chunks = sv->core->chunks;
+    st->graphs = sv->graphs;
+    st->completed = sv->core->completed;
     st->arena_in_use = sv->arena.in_use();
     return LB_OK;
 }
@@ -619,22 +472,10 @@ int lb_server_destroy(lb_server *sv)
     if (!sv) return LB_EINVAL;
     (void)hipSetDevice(sv->device);
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
-    while (!sv->inflight.empty()) {
-        bool r = false;
-        if (retire_front(sv, true, &r) != LB_OK || !r) break;
-    }
-    for (Job *j : sv->active) {
-        if (j->sim) lb_destroy(j->sim);
-        delete j;
-    }
-    for (Job *j : sv->queue) delete j;
-    for (Chunk &c : sv->inflight) {
-        for (Job *j : c.done) {
-            if (j->sim) lb_destroy(j->sim);
-            delete j;
-        }
-        (void)hipEventDestroy(c.ev);
-    }
+    delete sv->core;  // waits for the queued chunks and drops the rest
+    delete sv->be;
+    for (auto &g : sv->graph_refs)
+        if (g.first != sv->exec) (void)hipGraphExecDestroy(g.first);
     if (sv->exec) (void)hipGraphExecDestroy(sv->exec);
     if (sv->setup) (void)hipStreamSynchronize(sv->setup);
     if (sv->arena_mem) (void)hipFree(sv->arena_mem);
