@@ -568,3 +568,44 @@ def test_kernel_timing_changes_no_result():
     assert np.array_equal(out[0][1], out[1][1])
     for k in ("pos", "e", "v", "w"):
         assert np.array_equal(out[0][2][k], out[1][2][k])
+
+
+@pytest.mark.parametrize("storage,n", [("f32", 1023), ("f16", 1290)])
+def test_largest_box_translation_invariance(storage, n):
+    """The largest cubic box the 32-bit plane offsets allow (1023^3 in FP32,
+    1290^3 in FP16, 92-103 GB on the device). A prescribed squirmer
+    straddling the periodic z boundary, so that it touches the highest
+    offsets, must see exactly the forces of the same squirmer shifted by an
+    integer number of cells to the low planes. Positions, velocities and
+    lever arms are dyadic, so both runs do the same arithmetic; the force
+    sums are integer. Owners, forces, torques and the conversion parts must
+    agree bit for bit after every step."""
+    import torch
+    lbsq = gpu()
+    note("largest box %d^3 %s: translation invariance at the highest offsets" % (n, storage))
+    z_top, z_low = n - 1.625, 20.375  # the first straddles the periodic z boundary
+    shift = n - 22  # = z_top - z_low, whole cells
+    v, w = (2.0 ** -10, 0.0, 2.0 ** -11), (0.0, 0.0, 2.0 ** -12)
+    runs = []
+    for z in (z_top, z_low):
+        s = lbsq.Sim((n, n, n), storage=storage)
+        s.add_squirmer((n / 2 + 0.25, n / 2 - 0.125, z), (0.6, 0.8, 0.0), 6.0, B1=1e-3, beta=2.0,
+                       mode="prescribed", v=v, w=w)
+        out = []
+        for _ in range(6):
+            s.step(2)
+            F, T = s.force_torque(0)
+            fp = s.force_parts(0)
+            Fbb, Tbb, Fc, Tc = fp["Fbb"], fp["Tbb"], fp["Fc"], fp["Tc"]
+            b = s.body(0)
+            out.append((F, T, Fbb, Tbb, Fc, Tc, b["pos"], b["e"]))
+        assert s.info()["steps"] == 12
+        s.close()
+        runs.append(out)
+        torch.cuda.empty_cache()
+    for k, (a, b) in enumerate(zip(runs[0], runs[1])):
+        for q in range(6):
+            assert np.array_equal(a[q], b[q]), "step %d, quantity %d: %s vs %s" % (2 * k + 2, q, a[q], b[q])
+        d = np.mod(a[6] - b[6], n)
+        assert np.array_equal(d, np.array([0.0, 0.0, float(shift)])), d
+        assert np.array_equal(a[7], b[7])
