@@ -514,6 +514,37 @@ def test_reduced_precision_tube():
         assert abs(vg - vo) <= v_tol * abs(vo)
 
 
+@pytest.mark.slow
+def test_reduced_precision_256():
+    """The precision form on the 256^3 scene: a free squirmer R = 16 (beta =
+    -3) in a periodic 256^3 box, FP16 and BF16 deviation storage against the
+    FP64 oracle after 6 steps: identical owners, velocity-field L2 error
+    (FP16 <= 1e-3, BF16 <= 2e-2) and the swimmer's velocity (0.5%, 5%)."""
+    lbsq = gpu()
+    note("256^3 R=16, FP16 and BF16 storage, 6 steps")
+    shape = (256, 256, 256)
+    body = dict(pos=(127.3, 128.6, 128.2), e=(0.8, 0.6, 0.0), R=16.0, B1=1e-3, beta=-3.0)
+    o = O.OracleSim(*shape)
+    o.add_body(body["pos"], body["e"], body["R"], B1=body["B1"], beta=body["beta"])
+    o.step(6)
+    _, u_o, own_o = o.fields()
+    fl = own_o == 0
+    vo = o.body(0)["v"]
+    del o
+    for storage, l2_tol, v_tol in (("f16", 1e-3, 5e-3), ("bf16", 2e-2, 5e-2)):
+        s = lbsq.Sim(shape, storage=storage)
+        s.add_squirmer(body["pos"], body["e"], body["R"], B1=body["B1"], beta=body["beta"])
+        s.step(6)
+        _, u, own = s.fields()
+        assert np.array_equal(own, own_o)
+        l2 = np.linalg.norm((u - u_o)[:, fl]) / np.linalg.norm(u_o[:, fl])
+        vg = s.body(0)["v"]
+        s.close()
+        note("  %s L2 %.2e, velocity %s vs %s" % (storage, l2, vg, vo))
+        assert l2 <= l2_tol
+        assert np.linalg.norm(vg - vo) <= v_tol * np.linalg.norm(vo)
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_storage_rounds_to_nearest_even(storage):
     """Populations written through the ABI are stored as deviations
