@@ -112,3 +112,23 @@ def test_request_layout_matches_header():
     assert C.sizeof(lbsq.LbSquirmer) == 8 * (3 + 3 + 3 + 1 + 3 + 3 + 1)
     assert C.sizeof(lbsq.LbRequest) == 4 * 3 + 4 + 8 + 8 + 8 * C.sizeof(lbsq.LbSquirmer) + 8 + 8
     assert C.sizeof(lbsq.LbResult) == 8 * 2 + 4 * 2 + 8 * 2 + 6 * 8 * 3 * 8 + 8 * 4
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built library the binding raises instead of falling back
+    to anything else."""
+    monkeypatch.setattr(lbsq, "LIB_PATH", tmp_path / "liblbsq.so")
+    monkeypatch.setattr(lbsq, "_lib", None)
+    with pytest.raises(ImportError) as ei:
+        lbsq.load()
+    assert "not built" in str(ei.value)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
