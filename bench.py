@@ -267,6 +267,9 @@ def main():
                      "kernel": "k_fluid", "kernel_us": round(f32["kernel_us"], 2),
                      "bytes_per_update": BYTES_PER_UPDATE["f32"]},
         "conservation": f32["conservation"],
+        # swim speed along x at the end of the run over 2 B1 / 3, in this
+        # periodic box (its finite-size correction is not taken out here)
+        "swim_speed_over_v0": round(f32["v_over_v0"], 5),
     }
     if not args.no_fp16:
         f16 = run_gpu("f16", shape, args.R, args.beta, args.steps, args.warmup)
@@ -276,7 +279,8 @@ def main():
                                "kernel_gbs": round(f16["kernel_gbs"], 1), "bytes_per_update": 76,
                                "traffic": measured_traffic("f16", shape, args.R),
                                "speedup_vs_f32": round(f16["mlups"] / f32["mlups"], 3),
-                               "conservation": f16["conservation"]}
+                               "conservation": f16["conservation"],
+                               "swim_speed_over_v0": round(f16["v_over_v0"], 5)}
     if not args.no_hbm:
         # the same kernel where the in-place working set (1.28 GB) cannot
         # stay in the 256 MB last-level cache: the HBM-bound figure
