@@ -71,11 +71,11 @@ def copy_calibration(mib, reps=5):
     del src, dst
 
 
-def run_gpu(storage, shape, R, beta, steps, warmup):
+def run_gpu(storage, shape, R, beta, steps, warmup, layout="inplace"):
     import torch
     from paper_1903_04799_amd import Sim
     c = [s / 2.0 for s in shape]
-    sim = Sim(shape, storage=storage)
+    sim = Sim(shape, storage=storage, layout=layout)
     sim.add_squirmer(c, (1.0, 0.0, 0.0), R, B1=1e-3, beta=beta, mode="free")
     sim.step(warmup)
     sim.sync()
@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cubic box edge")
     ap.add_argument("--R", type=float, default=8.0)
     ap.add_argument("--beta", type=float, default=0.0)
+    ap.add_argument("--layout", choices=["inplace", "ab"], default="inplace",
+                    help="population layout of the main run: one buffer in place, or two buffers (pull)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
@@ -243,7 +245,7 @@ def main():
     shape = (args.n, args.n, args.n)
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
-    f32 = run_gpu("f32", shape, args.R, args.beta, args.steps, args.warmup)
+    f32 = run_gpu("f32", shape, args.R, args.beta, args.steps, args.warmup, args.layout)
     out = {
         "metric": "D3Q19 MLUPS FP32 vs FP16-storage; served sweep p50/p99 latency at fixed error",
         "value": round(f32["mlups"], 1),
@@ -259,6 +261,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "free squirmer in a periodic %d^3 box" % args.n, "box": list(shape),
                    "R": args.R, "beta": args.beta, "B1": 1e-3, "nu": 1 / 6, "storage": "f32 deviations",
+                   "layout": args.layout,
                    "n_fluid": f32["n_fluid"]},
         "roofline": {"bound": "hbm", "achieved": round(f32["kernel_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(f32["kernel_gbs"] / HBM_PEAK_GBS, 4),
@@ -272,7 +275,7 @@ def main():
         "swim_speed_over_v0": round(f32["v_over_v0"], 5),
     }
     if not args.no_fp16:
-        f16 = run_gpu("f16", shape, args.R, args.beta, args.steps, args.warmup)
+        f16 = run_gpu("f16", shape, args.R, args.beta, args.steps, args.warmup, args.layout)
         out["fp16_storage"] = {"value": round(f16["mlups"], 1), "unit": "MLUPS",
                                "ms_per_step": round(f16["ms_per_step"], 5),
                                "kernel_us": round(f16["kernel_us"], 2),
@@ -291,7 +294,14 @@ def main():
                             "ms_per_step": round(h["ms_per_step"], 5), "kernel_us": round(h["kernel_us"], 2),
                             "achieved_gbs": round(h["kernel_gbs"], 1),
                             "frac": round(h["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                            "working_set_mb": round(ws / 1e6, 1)}
+                            "working_set_mb": round(ws / 1e6, 1), "layout": "inplace"}
+        # the same with two population buffers (pull streaming), the layout
+        # for boxes that stream from HBM
+        h2 = run_gpu("f32", n2, 16.0, args.beta, 200, 50, "ab")
+        out["hbm_bound"]["ab"] = {"mlups": round(h2["mlups"], 1), "ms_per_step": round(h2["ms_per_step"], 5),
+                                  "kernel_us": round(h2["kernel_us"], 2), "achieved_gbs": round(h2["kernel_gbs"], 1),
+                                  "frac": round(h2["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                                  "working_set_mb": round(2 * ws / 1e6, 1)}
     if not args.no_serve:
         out["served"] = run_served(args.serve_requests, args.serve_seed, args.serve_chunk, args.serve_active,
                                    args.serve_budget_gb, ["f32"] if args.no_fp16 else ["f32", "f16"])

@@ -63,6 +63,7 @@ enum {
 enum { LB_STORAGE_F32 = 0, LB_STORAGE_F16 = 1, LB_STORAGE_BF16 = 2 };
 enum { LB_FREE = 0, LB_FIXED = 1, LB_PRESCRIBED = 2 };
 enum { LB_OWNER_FLUID = 0, LB_OWNER_WALL = 255 }; /* bodies: id + 1 */
+enum { LB_LAYOUT_INPLACE = 0, LB_LAYOUT_AB = 1 };
 
 typedef void *(*lb_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*lb_free_fn)(void *ptr, void *ctx);
@@ -87,7 +88,14 @@ typedef void (*lb_free_fn)(void *ptr, void *ctx);
  *   audit_every  fuse an FP64 mass/momentum audit and non-finite check into
  *                the collision every this many steps (0 = never);
  *   stream       hipStream_t to run on (NULL = the null stream);
- *   alloc, free, alloc_ctx  optional device allocator pair.               */
+ *   alloc, free, alloc_ctx  optional device allocator pair;
+ *   layout       LB_LAYOUT_INPLACE (0): one population buffer, each step
+ *                reads and rewrites it in place (half the memory; the
+ *                faster form while the buffer fits the 256 MB last-level
+ *                cache); LB_LAYOUT_AB (1): two buffers, each step pulls
+ *                from one and writes the other (the faster form for boxes
+ *                whose populations stream from HBM).  Results agree to
+ *                round-off; the checkpoint format is the same.            */
 typedef struct lb_params {
     int nx, ny, nz;
     double nu, magic, rho0;
@@ -100,6 +108,7 @@ typedef struct lb_params {
     lb_alloc_fn alloc;
     lb_free_fn free;
     void *alloc_ctx;
+    int layout;
 } lb_params;
 
 /* One spherical squirmer, eq. (squirmer) with beta = B2/B1.

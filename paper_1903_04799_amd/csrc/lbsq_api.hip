@@ -202,6 +202,7 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
     std::memset(&d, 0, sizeof(d));
     d.a = s->args;
     d.f = s->f;
+    d.f2 = s->f2;
     for (int k = 0; k < 2; ++k) {
         d.dens[k] = s->d_dens[k];
         d.own[k] = s->own[k];
@@ -269,10 +270,16 @@ int mirror_owner(lb_sim *s)
 // whether the last completed step had an even index (the in-place layout)
 bool after_even(const lb_sim *s) { return (s->steps & 1) == 1; }
 
+// The buffer holding the populations after the steps taken so far, and its
+// layout: in place the one buffer, by the parity of the last step; in the
+// pull layout the buffer the last step wrote (buffer steps & 1).
+void *pop_buf(const lb_sim *s) { return s->f2 && (s->steps & 1) ? s->f2 : s->f; }
+int pop_lay(const lb_sim *s) { return s->f2 ? LAY_AB : (after_even(s) ? LAY_AA_EVEN : LAY_AA_ODD); }
+
 // Link densities of the cells next to a body, for the next step.
 int refresh_dens(lb_sim *s)
 {
-    return launch_dens(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), s->d_dens[(s->steps + 1) & 1],
+    return launch_dens(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), s->d_dens[(s->steps + 1) & 1],
                        s->stream) == hipSuccess
                ? LB_OK
                : LB_EDEVICE;
@@ -330,6 +337,7 @@ int lb_destroy(lb_sim *s)
         (void)hipEventDestroy(e.second);
     }
     dev_free(s, s->f);
+    dev_free(s, s->f2);
     for (int k = 0; k < 2; ++k) {
         dev_free(s, s->d_dens[k]);
         dev_free(s, s->own[k]);
@@ -365,6 +373,7 @@ int lb_create(const lb_params *p, lb_sim **out)
     // one population plane must stay below 4 GiB (32-bit offsets in the kernels)
     if (plane_stride(n) * (p->storage == LB_STORAGE_F32 ? 4 : 2) > (uint64_t(1) << 32)) return LB_EINVAL;
     if ((p->alloc == nullptr) != (p->free == nullptr)) return LB_EINVAL;
+    if (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB) return LB_EINVAL;
 
     lb_sim *s = new (std::nothrow) lb_sim();
     if (!s) return LB_ENOMEM;
@@ -405,6 +414,7 @@ int lb_create(const lb_params *p, lb_sim **out)
 
     const size_t fbytes = size_t(Q) * bx.stride * s->esize;
     s->f = dev_alloc(s, fbytes);
+    if (p->layout == LB_LAYOUT_AB) s->f2 = dev_alloc(s, fbytes);
     for (int k = 0; k < 2; ++k) {
         s->d_dens[k] = static_cast<float *>(dev_alloc(s, size_t(n) * sizeof(float)));
         s->own[k] = static_cast<uint8_t *>(dev_alloc(s, n));
@@ -417,12 +427,13 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
     s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
     s->d_desc = static_cast<SimDesc *>(dev_alloc(s, sizeof(SimDesc)));
-    if (!s->f || !s->d_dens[0] || !s->d_dens[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
+    if (!s->f || (p->layout == LB_LAYOUT_AB && !s->f2) || !s->d_dens[0] || !s->d_dens[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
         !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err || !s->d_desc) {
         lb_destroy(s);
         return LB_ENOMEM;
     }
     hipError_t e = hipMemsetAsync(s->f, 0, fbytes, s->stream);
+    if (e == hipSuccess && s->f2) e = hipMemsetAsync(s->f2, 0, fbytes, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_acc, 0, NACCSET * ACCSET_SIZE * sizeof(unsigned long long), s->stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(s->d_dens[k], 0, size_t(n) * sizeof(float), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->own[0], 0, n, s->stream);
@@ -566,7 +577,7 @@ int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
     uint8_t *d_o = static_cast<uint8_t *>(dev_alloc(s, n));
     int rc = LB_OK;
     if (!d_rho || !d_u || !d_o) rc = LB_ENOMEM;
-    if (rc == LB_OK && launch_fields(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), d_rho, d_u, d_o, s->stream) !=
+    if (rc == LB_OK && launch_fields(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), d_rho, d_u, d_o, s->stream) !=
                            hipSuccess)
         rc = LB_EDEVICE;
     if (rc == LB_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LB_EDEVICE;
@@ -683,7 +694,7 @@ int lb_read_populations(lb_sim *s, double *f)
     if (!buf) return LB_ENOMEM;
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
-        if (launch_plane(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), i, buf, 1, s->stream) !=
+        if (launch_plane(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), i, buf, 1, s->stream) !=
                 hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess ||
             hipMemcpy(f + size_t(i) * n, buf, size_t(n) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
@@ -704,7 +715,7 @@ int lb_write_populations(lb_sim *s, const double *f)
     int rc = LB_OK;
     for (int i = 0; i < Q && rc == LB_OK; ++i) {
         if (hipMemcpy(buf, f + size_t(i) * n, size_t(n) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            launch_plane(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), i, buf, 0, s->stream) !=
+            launch_plane(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), i, buf, 0, s->stream) !=
                 hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess)
             rc = LB_EDEVICE;
@@ -718,7 +729,7 @@ static int audit_now(lb_sim *s, double out[5])
 {
     int st = sync_check(s);
     if (st != LB_OK) return st;
-    if (launch_audit(s->p.storage, s->args, s->f, s->own[s->cur], after_even(s), s->d_audit_part, s->d_audit_out,
+    if (launch_audit(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), s->d_audit_part, s->d_audit_out,
                      s->d_err, s->stream) != hipSuccess)
         return LB_EDEVICE;
     st = sync_check(s);
@@ -762,6 +773,8 @@ struct StateHeader {
     int32_t nx, ny, nz, storage, scale_log2, nbody;
     int64_t steps;
     uint64_t pop_bytes;
+    int32_t layout;  // the populations are saved in the handle's own layout
+    int32_t pad;
 };
 
 static constexpr uint64_t STATE_MAGIC = 0x34717362'6c62ull;
@@ -787,11 +800,12 @@ int lb_save_state(lb_sim *s, void *buf, size_t bytes)
     if (st != LB_OK) return st;
     if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
     StateHeader h{STATE_MAGIC, s->p.nx, s->p.ny, s->p.nz, s->p.storage, s->p.scale_log2,
-                  int32_t(s->bodies.size()), s->steps, uint64_t(Q) * s->args.box.stride * s->esize};
+                  int32_t(s->bodies.size()), s->steps, uint64_t(Q) * s->args.box.stride * s->esize,
+                  s->p.layout, 0};
     char *p = static_cast<char *>(buf);
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
-    if (hipMemcpy(p, s->f, h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
+    if (hipMemcpy(p, pop_buf(s), h.pop_bytes, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
     if (hipMemcpy(p, s->own[s->cur], s->args.box.n, hipMemcpyDeviceToHost) != hipSuccess) return LB_EDEVICE;
     p += s->args.box.n;
@@ -808,7 +822,7 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     std::memcpy(&h, buf, sizeof(h));
     if (h.magic != STATE_MAGIC || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz ||
         h.storage != s->p.storage || h.scale_log2 != s->p.scale_log2 || h.nbody < 0 || h.nbody > MAXB ||
-        h.pop_bytes != uint64_t(Q) * s->args.box.stride * s->esize)
+        h.pop_bytes != uint64_t(Q) * s->args.box.stride * s->esize || h.layout != s->p.layout)
         return LB_EINVAL;
     const size_t need = sizeof(h) + h.pop_bytes + s->args.box.n + size_t(h.nbody) * sizeof(DevBody) + ACC_BYTES;
     if (bytes < need) return LB_EINVAL;
@@ -816,7 +830,8 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     if (st != LB_OK) return st;
     const char *p = static_cast<const char *>(buf) + sizeof(h);
     s->cur = int(h.steps & 1);
-    if (hipMemcpy(s->f, p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    void *dst = s->f2 && (h.steps & 1) ? s->f2 : s->f;  // the buffer that holds step h.steps
+    if (hipMemcpy(dst, p, h.pop_bytes, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     p += h.pop_bytes;
     for (int k = 0; k < 2; ++k)
         if (hipMemcpy(s->own[k], p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;

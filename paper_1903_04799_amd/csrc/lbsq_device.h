@@ -177,6 +177,14 @@ constexpr int ACCSET_SIZE = NCOPY * MAXB * NACC;  // integers per set
 // up to this many bodies the last boundary block of the fluid launch does the
 // body update (staged in LDS); more bodies take a separate one-block launch
 constexpr int FUSE_MAX = 8;
+
+// Population layouts.  In place (one buffer): after an even step f*_j(x) is
+// in plane jbar at x, after an odd step (and initially) in plane j at x + c_j.
+// Pull (two buffers): step t reads buffer t & 1 and writes the other, and
+// f*_j(x) is in plane j at x of the buffer last written.
+constexpr int LAY_AA_ODD = 0, LAY_AA_EVEN = 1, LAY_AB = 2;
+// how a step streams: in place with an even or odd index, or pull
+constexpr int STEP_AA_EVEN = 0, STEP_AA_ODD = 1, STEP_AB = 2;
 constexpr double FX_SCALE = 17592186044416.0;  // 2^44
 __device__ __forceinline__ long long to_fx(double v) { return __double2ll_rn(v * FX_SCALE); }
 __device__ __forceinline__ double from_fx(unsigned long long v) { return double(static_cast<long long>(v)) / FX_SCALE; }

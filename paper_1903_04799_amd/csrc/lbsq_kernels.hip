@@ -351,10 +351,13 @@ struct Planes {
 };
 
 // Slot of the post-collision population f*_j of cell (x, y, z) between steps,
-// after an even (after_even) or odd step.
-__device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y, int z, bool after_even)
+// by layout: in place after an odd step (LAY_AA_ODD) or an even one
+// (LAY_AA_EVEN), or in the buffer the last step wrote in the two-buffer pull
+// layout (LAY_AB).
+__device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y, int z, int lay)
 {
-    if (after_even) return uint64_t(opp(j)) * bx.stride + cell_of(bx, x, y, z);
+    if (lay == LAY_AB) return uint64_t(j) * bx.stride + cell_of(bx, x, y, z);
+    if (lay == LAY_AA_EVEN) return uint64_t(opp(j)) * bx.stride + cell_of(bx, x, y, z);
     return uint64_t(j) * bx.stride + cell_of(bx, wrap_small(x + rcx(j), bx.nx), wrap_small(y + rcy(j), bx.ny),
                                              wrap_small(z + rcz(j), bx.nz));
 }
@@ -362,10 +365,13 @@ __device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y
 // ---------------------------------------------------------------------------
 // the hot loop: every fluid cell without a body neighbour
 
-template <class S, bool AUDIT, bool FORCE, bool ODD>
-__device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
-                                                     double *__restrict__ audit_part, uint32_t blk)
+template <class S, bool AUDIT, bool FORCE, int MODE>
+__device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typename S::T> F, int64_t to_write,
+                                                     gptr<const uint8_t> own, double *__restrict__ audit_part,
+                                                     uint32_t blk)
 {
+    // F is the buffer read (and, in place, written); the pull layout writes
+    // the other buffer, to_write bytes away
     const Planes<typename S::T> P(F, a.box.stride);
     const uint32_t idx = blk * BLOCK + threadIdx.x;
     const uint8_t o = idx < a.box.n ? own[idx] : OWN_WALL;
@@ -376,7 +382,8 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
         if (o == OWN_FLUID) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if (ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i));
+                if (MODE == STEP_AA_ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i));
+                else if (MODE == STEP_AB) f[i] = ld_plane<S>(P.p[i], nb.src(i));
                 else f[i] = ld_plane<S>(P.p[i], idx);
             }
         } else {
@@ -385,7 +392,9 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const uint32_t s = nb.src(i);
-                if (ODD == is_fluid(own[s])) f[i] = ld_plane<S>(P.p[opp(i)], s);
+                const bool fl = is_fluid(own[s]);
+                if (MODE == STEP_AB) f[i] = fl ? ld_plane<S>(P.p[i], s) : ld_plane<S>(P.p[opp(i)], idx);
+                else if ((MODE == STEP_AA_ODD) == fl) f[i] = ld_plane<S>(P.p[opp(i)], s);
                 else f[i] = ld_plane<S>(P.p[i], idx);
             }
         }
@@ -393,7 +402,9 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
         collide<S, FORCE>(a, f, out);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            if (ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i]);
+            if (MODE == STEP_AA_ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i]);
+            else if (MODE == STEP_AB)
+                st_plane_nt<S>((gptr<typename S::T>)((gptr<char>)P.p[i] + to_write), idx, out[i]);
             else st_plane_nt<S>(P.p[opp(i)], idx, out[i]);
         }
         if (AUDIT) audit_add<S>(a, out, am);
@@ -669,8 +680,9 @@ __device__ __forceinline__ void add_performed(unsigned long long *p, unsigned lo
     asm volatile("" ::"v"(old));
 }
 
-template <class S, bool AUDIT, bool FORCE, bool ODD>
-__device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename S::T> F, gptr<const uint8_t> own,
+template <class S, bool AUDIT, bool FORCE, int MODE>
+__device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename S::T> F, int64_t to_write,
+                                               gptr<const uint8_t> own,
                                                const DevBody *__restrict__ cur, int nbody,
                                                const int4 *__restrict__ blkinfo, const uint32_t *__restrict__ shell,
                                                unsigned long long *__restrict__ acc, gptr<const float> dens_prev,
@@ -721,8 +733,14 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     const uint8_t os = (valid && i > 0) ? own[s] : OWN_FLUID;
     float f_in = 0.0f, f_ref = 0.0f, dprev = 0.0f;
     if (valid) {
-        f_in = S::ld(F[ODD ? opp(i) * st + s : i * st + c], a.inv_scale);
-        f_ref = S::ld(F[ODD ? i * st + c : opp(i) * st + s], a.inv_scale);
+        constexpr bool ODD = MODE == STEP_AA_ODD;
+        if (MODE == STEP_AB) {
+            f_in = S::ld(F[i * st + s], a.inv_scale);
+            f_ref = S::ld(F[opp(i) * st + c], a.inv_scale);
+        } else {
+            f_in = S::ld(F[ODD ? opp(i) * st + s : i * st + c], a.inv_scale);
+            f_ref = S::ld(F[ODD ? i * st + c : opp(i) * st + s], a.inv_scale);
+        }
         dprev = dens_prev[c];
     }
     const bool cand = oc == OWN_NB_BODY;
@@ -759,10 +777,16 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     if (active) {
         const typename S::T o = S::st(collide_one<FORCE>(a, s_f[cl], i), a.scale);
         s_o[cl][i] = S::ld(o, a.inv_scale);
-        const uint64_t at = ODD ? i * st + cell_of(bx, wrap_small(x + rcx(i), bx.nx), wrap_small(y + rcy(i), bx.ny),
-                                                   wrap_small(z + rcz(i), bx.nz))
-                                : opp(i) * st + c;
-        __builtin_nontemporal_store(o, &F[at]);
+        if (MODE == STEP_AA_ODD) {
+            const uint64_t at = i * st + cell_of(bx, wrap_small(x + rcx(i), bx.nx), wrap_small(y + rcy(i), bx.ny),
+                                                 wrap_small(z + rcz(i), bx.nz));
+            __builtin_nontemporal_store(o, &F[at]);
+        } else if (MODE == STEP_AB) {
+            const gptr<typename S::T> W = (gptr<typename S::T>)((gptr<char>)F + to_write);
+            __builtin_nontemporal_store(o, &W[i * st + c]);
+        } else {
+            __builtin_nontemporal_store(o, &F[opp(i) * st + c]);
+        }
     }
     __syncthreads();
     if (active && i == 0) {
@@ -857,25 +881,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AUDIT ? 4
     const int64_t t = d.t0 + k;
     if (t >= d.t_end) return;
     const int c = int(t & 1);
-    const gptr<T> F = as_global(static_cast<T *>(d.f));
+    // in place the step's parity picks the streaming direction; the pull
+    // layout reads buffer c and writes the other.  Either is the same for
+    // every block of a simulation.
+    const bool ab = d.f2 != nullptr;
+    const gptr<T> F = as_global(static_cast<T *>(ab && c ? d.f2 : d.f));
+    const int64_t to_write = ab ? (c ? static_cast<const char *>(d.f) - static_cast<const char *>(d.f2)
+                                     : static_cast<const char *>(d.f2) - static_cast<const char *>(d.f))
+                                : 0;
     const gptr<const uint8_t> own = as_global(static_cast<const uint8_t *>(d.own[c]));
     const int blk = int(blockIdx.x - m.fluid0[si]);
-    // the step's parity picks the streaming direction of the in-place
-    // layout; it is the same for every block of a simulation
     if (blk < d.nblk_b) {
         const gptr<const float> dp = as_global(static_cast<const float *>(d.dens[c ^ 1]));
         const gptr<float> dc = as_global(d.dens[c]);
-        if (c)
-            boundary_block<S, AUDIT, FORCE, true>(d.a, F, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
-                                                  acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
+        double *ap = d.audit_part + size_t(d.nblk_s) * 5;
+        if (ab)
+            boundary_block<S, AUDIT, FORCE, STEP_AB>(d.a, F, to_write, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
+                                                     acc_set(d.acc, t), dp, dc, ap, blk);
+        else if (c)
+            boundary_block<S, AUDIT, FORCE, STEP_AA_ODD>(d.a, F, 0, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
+                                                         acc_set(d.acc, t), dp, dc, ap, blk);
         else
-            boundary_block<S, AUDIT, FORCE, false>(d.a, F, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
-                                                   acc_set(d.acc, t), dp, dc, d.audit_part + size_t(d.nblk_s) * 5, blk);
+            boundary_block<S, AUDIT, FORCE, STEP_AA_EVEN>(d.a, F, 0, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
+                                                          acc_set(d.acc, t), dp, dc, ap, blk);
         if (d.nbody <= FUSE_MAX) arrive_and_update(d, c, t);
+    } else if (ab) {
+        stream_collide_block<S, AUDIT, FORCE, STEP_AB>(d.a, F, to_write, own, d.audit_part, uint32_t(blk - d.nblk_b));
     } else if (c) {
-        stream_collide_block<S, AUDIT, FORCE, true>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));
+        stream_collide_block<S, AUDIT, FORCE, STEP_AA_ODD>(d.a, F, 0, own, d.audit_part, uint32_t(blk - d.nblk_b));
     } else {
-        stream_collide_block<S, AUDIT, FORCE, false>(d.a, F, own, d.audit_part, uint32_t(blk - d.nblk_b));
+        stream_collide_block<S, AUDIT, FORCE, STEP_AA_EVEN>(d.a, F, 0, own, d.audit_part, uint32_t(blk - d.nblk_b));
     }
 }
 
@@ -944,7 +979,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                                               const int *__restrict__ ids, const int *__restrict__ start, int nlist,
                                               unsigned long long *__restrict__ acc_conv,
                                               gptr<const uint8_t> own_old, gptr<uint8_t> own_new,
-                                              gptr<typename S::T> A, bool after_even, gptr<float> dens,
+                                              gptr<typename S::T> A, int lay, gptr<float> dens,
                                               int *__restrict__ err, int blk)
 {
     extern __shared__ double lds_dyn[];  // nbody GeoBody
@@ -976,7 +1011,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
         const bool uncovered = is_body(s_oo[sl.cl][0]) && s_on[sl.cl][0] == OWN_FLUID;
         if (uncovered && i > 0 && s_on[sl.cl][i] == OWN_FLUID && is_fluid(oo)) {
             r = 0.0;
-            for (int j = 0; j < Q; ++j) r += double(S::ld(A[post_slot(bx, j, nxc, nyc, nzc, after_even)], a.inv_scale));
+            for (int j = 0; j < Q; ++j) r += double(S::ld(A[post_slot(bx, j, nxc, nyc, nzc, lay)], a.inv_scale));
             r += a.rho0d;
         }
         s_rho[sl.cl][i] = r;
@@ -994,7 +1029,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
             if (is_fluid(old)) {
                 // covered: the body swallows the cell's populations
                 for (int j = 1; j < Q; ++j) {
-                    const double fj = S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)], a.inv_scale);
+                    const double fj = S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, lay)], a.inv_scale);
                     p[0] += rcx(j) * fj;
                     p[1] += rcy(j) * fj;
                     p[2] += rcz(j) * fj;
@@ -1035,7 +1070,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                     const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
                     const double w = j == 0 ? 1.0 / 3.0 : (j <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
                     const double dev = w * (rb - a.rho0d) + w * rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                    A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)] = S::st(float(dev), a.scale);
+                    A[post_slot(bx, j, sl.x, sl.y, sl.z, lay)] = S::st(float(dev), a.scale);
                 }
                 p[0] = rb * u[0];
                 p[1] = rb * u[1];
@@ -1047,7 +1082,7 @@ __device__ __forceinline__ void geoconv_block(const StepArgs &a, const DevBody *
                 // to one): the density its links will use in the next step,
                 // summed as the boundary kernel sums what it stores
                 float dr = 0.0f;
-                for (int j = 0; j < Q; ++j) dr += S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, after_even)], a.inv_scale);
+                for (int j = 0; j < Q; ++j) dr += S::ld(A[post_slot(bx, j, sl.x, sl.y, sl.z, lay)], a.inv_scale);
                 dens[c] = dr;
             }
         }
@@ -1078,9 +1113,14 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D
     const int64_t t = d.t0 + k;
     if (t >= d.t_end) return;
     const int c = int(t & 1);
+    // the populations after step t: in place in the one buffer, or in the
+    // buffer step t wrote
+    const bool ab = d.f2 != nullptr;
+    void *post = ab && c == 0 ? d.f2 : d.f;
+    const int lay = ab ? LAY_AB : (c == 0 ? LAY_AA_EVEN : LAY_AA_ODD);
     geoconv_block<S>(d.a, d.bodies[c], d.bodies[c ^ 1], d.nbody, d.mov_ids, d.mov_start, d.nmov,
                      acc_set(d.acc, t + 1), as_global(static_cast<const uint8_t *>(d.own[c])), as_global(d.own[c ^ 1]),
-                     as_global(static_cast<typename S::T *>(d.f)), c == 0, as_global(d.dens[c]), d.err,
+                     as_global(static_cast<typename S::T *>(post)), lay, as_global(d.dens[c]), d.err,
                      int(blockIdx.x - m.geo0[si]));
 }
 
@@ -1136,7 +1176,7 @@ __device__ __forceinline__ void coords(const Box &bx, uint32_t c, int &x, int &y
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_audit(StepArgs a, const typename S::T *__restrict__ A,
-                                                 const uint8_t *__restrict__ own, bool after_even,
+                                                 const uint8_t *__restrict__ own, int lay,
                                                  double *__restrict__ part)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -1145,7 +1185,7 @@ __global__ __launch_bounds__(BLOCK) void k_audit(StepArgs a, const typename S::T
         int x, y, z;
         coords(a.box, c, x, y, z);
         for (int i = 0; i < Q; ++i) {
-            const double v = S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
+            const double v = S::ld(A[post_slot(a.box, i, x, y, z, lay)], a.inv_scale);
             am[0] += v;
             am[1] += cx(i) * v;
             am[2] += cy(i) * v;
@@ -1180,7 +1220,7 @@ __global__ __launch_bounds__(BLOCK) void k_audit_final(const double *__restrict_
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::T *__restrict__ A,
-                                                  const uint8_t *__restrict__ own, bool after_even,
+                                                  const uint8_t *__restrict__ own, int lay,
                                                   double *__restrict__ rho, double *__restrict__ u,
                                                   uint8_t *__restrict__ own_out)
 {
@@ -1197,7 +1237,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
     int x, y, z;
     coords(a.box, c, x, y, z);
     for (int i = 0; i < Q; ++i) {
-        const double v = S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
+        const double v = S::ld(A[post_slot(a.box, i, x, y, z, lay)], a.inv_scale);
         r += v;
         j[0] += cx(i) * v;
         j[1] += cy(i) * v;
@@ -1213,7 +1253,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
 // permutations of the buffer.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_plane_to_f64(StepArgs a, const typename S::T *__restrict__ A,
-                                                        const uint8_t *__restrict__ own, bool after_even, int i,
+                                                        const uint8_t *__restrict__ own, int lay, int i,
                                                         double *__restrict__ out)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -1221,20 +1261,20 @@ __global__ __launch_bounds__(BLOCK) void k_plane_to_f64(StepArgs a, const typena
     int x, y, z;
     coords(a.box, c, x, y, z);
     out[c] = is_fluid(own[c])
-                 ? wgt(i) * a.rho0d + double(S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale))
+                 ? wgt(i) * a.rho0d + double(S::ld(A[post_slot(a.box, i, x, y, z, lay)], a.inv_scale))
                  : 0.0;
 }
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_plane_from_f64(StepArgs a, typename S::T *__restrict__ A,
-                                                          const uint8_t *__restrict__ own, bool after_even, int i,
+                                                          const uint8_t *__restrict__ own, int lay, int i,
                                                           const double *__restrict__ in)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.box.n) return;
     int x, y, z;
     coords(a.box, c, x, y, z);
-    A[post_slot(a.box, i, x, y, z, after_even)] =
+    A[post_slot(a.box, i, x, y, z, lay)] =
         is_fluid(own[c]) ? S::st(float(in[c] - wgt(i) * a.rho0d), a.scale) : S::st(0.0f, a.scale);
 }
 
@@ -1242,7 +1282,7 @@ __global__ __launch_bounds__(BLOCK) void k_plane_from_f64(StepArgs a, typename S
 // every cell next to a body, for the links of the next step.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_dens(StepArgs a, const typename S::T *__restrict__ A,
-                                                const uint8_t *__restrict__ own, bool after_even,
+                                                const uint8_t *__restrict__ own, int lay,
                                                 float *__restrict__ dens)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -1250,7 +1290,7 @@ __global__ __launch_bounds__(BLOCK) void k_dens(StepArgs a, const typename S::T 
     int x, y, z;
     coords(a.box, c, x, y, z);
     float dr = 0.0f;
-    for (int i = 0; i < Q; ++i) dr += S::ld(A[post_slot(a.box, i, x, y, z, after_even)], a.inv_scale);
+    for (int i = 0; i < Q; ++i) dr += S::ld(A[post_slot(a.box, i, x, y, z, lay)], a.inv_scale);
     dens[c] = dr;
 }
 
@@ -1341,86 +1381,86 @@ hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int si
 }
 
 template <class S>
-static hipError_t launch_audit_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, double *part,
+static hipError_t launch_audit_t(const StepArgs &a, const void *A, const uint8_t *own, int lay, double *part,
                                  double *out, int *err, hipStream_t s)
 {
     const int nblk = int((a.box.n + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_audit<S>, dim3(nblk), dim3(BLOCK), 0, s, a, static_cast<const typename S::T *>(A), own,
-                       after_even, part);
+                       lay, part);
     hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, s, part, nblk, out, err);
     return hipGetLastError();
 }
 
-hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
                         double *part, double *out, int *err, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_audit_t<StF16>(a, A, own, after_even, part, out, err, s);
-    case 2: return launch_audit_t<StBF16>(a, A, own, after_even, part, out, err, s);
-    default: return launch_audit_t<StF32>(a, A, own, after_even, part, out, err, s);
+    case 1: return launch_audit_t<StF16>(a, A, own, lay, part, out, err, s);
+    case 2: return launch_audit_t<StBF16>(a, A, own, lay, part, out, err, s);
+    default: return launch_audit_t<StF32>(a, A, own, lay, part, out, err, s);
     }
 }
 
 template <class S>
-static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, double *rho,
+static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, int lay, double *rho,
                                   double *u, uint8_t *own_out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fields<S>, dim3((a.box.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
-                       static_cast<const typename S::T *>(A), own, after_even, rho, u, own_out);
+                       static_cast<const typename S::T *>(A), own, lay, rho, u, own_out);
     return hipGetLastError();
 }
 
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
                          double *rho, double *u, uint8_t *own_out, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_fields_t<StF16>(a, A, own, after_even, rho, u, own_out, s);
-    case 2: return launch_fields_t<StBF16>(a, A, own, after_even, rho, u, own_out, s);
-    default: return launch_fields_t<StF32>(a, A, own, after_even, rho, u, own_out, s);
+    case 1: return launch_fields_t<StF16>(a, A, own, lay, rho, u, own_out, s);
+    case 2: return launch_fields_t<StBF16>(a, A, own, lay, rho, u, own_out, s);
+    default: return launch_fields_t<StF32>(a, A, own, lay, rho, u, own_out, s);
     }
 }
 
 template <class S>
-static hipError_t launch_plane_t(const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i, double *buf,
+static hipError_t launch_plane_t(const StepArgs &a, void *A, const uint8_t *own, int lay, int i, double *buf,
                                  int to_f64, hipStream_t s)
 {
     using T = typename S::T;
     const dim3 g((a.box.n + BLOCK - 1) / BLOCK);
     if (to_f64)
-        hipLaunchKernelGGL(k_plane_to_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<const T *>(A), own, after_even, i,
+        hipLaunchKernelGGL(k_plane_to_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<const T *>(A), own, lay, i,
                            buf);
     else
-        hipLaunchKernelGGL(k_plane_from_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<T *>(A), own, after_even, i,
+        hipLaunchKernelGGL(k_plane_from_f64<S>, g, dim3(BLOCK), 0, s, a, static_cast<T *>(A), own, lay, i,
                            static_cast<const double *>(buf));
     return hipGetLastError();
 }
 
-hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i,
+hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, int lay, int i,
                         double *buf, int to_f64, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_plane_t<StF16>(a, A, own, after_even, i, buf, to_f64, s);
-    case 2: return launch_plane_t<StBF16>(a, A, own, after_even, i, buf, to_f64, s);
-    default: return launch_plane_t<StF32>(a, A, own, after_even, i, buf, to_f64, s);
+    case 1: return launch_plane_t<StF16>(a, A, own, lay, i, buf, to_f64, s);
+    case 2: return launch_plane_t<StBF16>(a, A, own, lay, i, buf, to_f64, s);
+    default: return launch_plane_t<StF32>(a, A, own, lay, i, buf, to_f64, s);
     }
 }
 
 template <class S>
-static hipError_t launch_dens_t(const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+static hipError_t launch_dens_t(const StepArgs &a, const void *A, const uint8_t *own, int lay, float *dens,
                                 hipStream_t s)
 {
     hipLaunchKernelGGL(k_dens<S>, dim3((a.box.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
-                       static_cast<const typename S::T *>(A), own, after_even, dens);
+                       static_cast<const typename S::T *>(A), own, lay, dens);
     return hipGetLastError();
 }
 
-hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay, float *dens,
                        hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_dens_t<StF16>(a, A, own, after_even, dens, s);
-    case 2: return launch_dens_t<StBF16>(a, A, own, after_even, dens, s);
-    default: return launch_dens_t<StF32>(a, A, own, after_even, dens, s);
+    case 1: return launch_dens_t<StF16>(a, A, own, lay, dens, s);
+    case 2: return launch_dens_t<StBF16>(a, A, own, lay, dens, s);
+    default: return launch_dens_t<StF32>(a, A, own, lay, dens, s);
     }
 }
 

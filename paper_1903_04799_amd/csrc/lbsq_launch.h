@@ -39,7 +39,8 @@ constexpr int MAXSIM = 64;
 // the conversion force of this move, set (t+2) % 3 is zeroed.
 struct SimDesc {
     StepArgs a;
-    void *f;  // the population buffer (in-place layout)
+    void *f;   // the population buffer (the first of two in the pull layout)
+    void *f2;  // the second buffer of the two-buffer pull layout; null in place
     float *dens[2];
     uint8_t *own[2];
     DevBody *bodies[2];
@@ -98,15 +99,16 @@ hipError_t launch_batch_step(int storage, const BatchLaunch &L);
 hipError_t launch_classify(const Box &bx, uint8_t *own, hipStream_t s);
 hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int side, uint8_t *own, int check,
                              int *err, hipStream_t s);
-// Readouts of the state after a completed step; after_even tells the
-// in-place layout (the last step's index was even).
-hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+// Readouts of the state after a completed step: A is the buffer holding it
+// and lay its layout (LAY_AA_ODD / LAY_AA_EVEN: in place, after an odd or
+// even step; LAY_AB: the buffer the last step of the pull layout wrote).
+hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
                         double *part, double *out, int *err, hipStream_t s);
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even,
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
                          double *rho, double *u, uint8_t *own_out, hipStream_t s);
-hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, bool after_even, int i,
+hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, int lay, int i,
                         double *buf, int to_f64, hipStream_t s);
-hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, bool after_even, float *dens,
+hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay, float *dens,
                        hipStream_t s);
 hipError_t launch_link_mask(const Box &bx, const uint8_t *own, uint32_t *mask, hipStream_t s);
 

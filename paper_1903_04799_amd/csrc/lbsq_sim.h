@@ -30,6 +30,7 @@ struct lb_sim {
     // index cur holding the current time level; link densities of the
     // previous and current step
     void *f = nullptr;
+    void *f2 = nullptr;  // the second buffer of the pull layout (LB_LAYOUT_AB)
     float *d_dens[2] = {nullptr, nullptr};
     uint8_t *own[2] = {nullptr, nullptr};
     lbsq::DevBody *d_bodies[2] = {nullptr, nullptr};

@@ -21,6 +21,7 @@ LIB_PATH = Path(__file__).resolve().parent / "liblbsq.so"
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EGEOM, LB_ESTATE, LB_ENAN, LB_EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 LB_ECANCELED = -8
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+LAYOUT = {"inplace": 0, "ab": 1}
 MODES = {"free": 0, "fixed": 1, "prescribed": 2}
 Q = 19
 
@@ -46,7 +47,7 @@ class LbParams(C.Structure):
                 ("wca_sigma", C.c_double), ("wca_eps", C.c_double),
                 ("g", C.c_double * 3), ("audit_every", C.c_int),
                 ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("layout", C.c_int)]
 
 
 class LbSquirmer(C.Structure):
@@ -212,7 +213,7 @@ class Sim:
 
     def __init__(self, shape, nu=1.0 / 6.0, magic=3.0 / 16.0, rho0=1.0, storage="f32",
                  scale_log2=None, wca_sigma=1.0, wca_eps=0.01, g=(0.0, 0.0, 0.0), audit_every=0,
-                 stream=None, torch_memory=True):
+                 stream=None, torch_memory=True, layout="inplace"):
         L = load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -227,6 +228,7 @@ class Sim:
         p.wca_sigma, p.wca_eps = float(wca_sigma), float(wca_eps)
         p.g = (C.c_double * 3)(*[float(x) for x in g])
         p.audit_every = int(audit_every)
+        p.layout = LAYOUT[layout]
         self._mem = None
         torch = _torch_cuda()
         if stream is None and torch is not None:

@@ -38,10 +38,16 @@ def note(msg):
     sys.stdout.flush()
 
 
-def make_pair(shape, bodies=(), mask=None, g=(0.0, 0.0, 0.0), storage="f32", f0=None, audit_every=0):
+# the two population layouts: one buffer updated in place, or two buffers
+# with pull streaming
+LAYOUTS = ["inplace", "ab"]
+
+
+def make_pair(shape, bodies=(), mask=None, g=(0.0, 0.0, 0.0), storage="f32", f0=None, audit_every=0,
+              layout="inplace"):
     lbsq = gpu()
     o = O.OracleSim(*shape, g=g)
-    s = lbsq.Sim(shape, storage=storage, g=g, audit_every=audit_every)
+    s = lbsq.Sim(shape, storage=storage, g=g, audit_every=audit_every, layout=layout)
     if mask is not None:
         o.set_static_mask(mask)
         s.set_static_mask(mask)
@@ -102,11 +108,12 @@ def random_state(shape, seed, amp=1e-3):
 
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("shape", [(23, 19, 17), (64, 8, 6)])
-def test_periodic_fluid_random_state(shape):
-    note("periodic fluid %s" % (shape,))
+def test_periodic_fluid_random_state(shape, layout):
+    note("periodic fluid %s, %s" % (shape, layout))
     f0 = random_state(shape, 3)
-    o, s = make_pair(shape, f0=f0)
+    o, s = make_pair(shape, f0=f0, layout=layout)
     for _ in range(3):
         o.step(10)
         s.step(10)
@@ -116,10 +123,11 @@ def test_periodic_fluid_random_state(shape):
     assert np.abs(fg - fo).max() <= 1e-8
 
 
-def test_rest_state_is_bitwise_fixed_point():
-    note("rest state with a fixed no-slip sphere")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rest_state_is_bitwise_fixed_point(layout):
+    note("rest state with a fixed no-slip sphere, %s" % layout)
     lbsq = gpu()
-    s = lbsq.Sim((24, 24, 24))
+    s = lbsq.Sim((24, 24, 24), layout=layout)
     s.add_squirmer((12, 12, 12), (1, 0, 0), 5.0, B1=0.0, mode="fixed")
     f0 = s.populations()
     s.step(50)
@@ -131,13 +139,14 @@ def test_rest_state_is_bitwise_fixed_point():
     assert np.abs(F).max() < 1e-13 and np.abs(T).max() < 1e-12
 
 
-def test_config_small_free_squirmer():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_config_small_free_squirmer(layout):
     """32^3 box, R=4 neutral squirmer at the centre swimming along +x,
     B1 = 1e-3, 200 steps (the oracle-size configuration)."""
-    note("32^3 R=4 beta=0 free, 200 steps")
+    note("32^3 R=4 beta=0 free, 200 steps, %s" % layout)
     shape = (32, 32, 32)
     body = dict(pos=(16.0, 16.0, 16.0), e=(1, 0, 0), R=4.0, B1=1e-3, beta=0.0)
-    o, s = make_pair(shape, [body])
+    o, s = make_pair(shape, [body], layout=layout)
     for _ in range(4):
         o.step(50)
         s.step(50)
@@ -150,13 +159,14 @@ def test_config_small_free_squirmer():
     assert np.abs(P_g - P_o).max() <= 1e-5 * np.abs(P_o).max()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("beta", [-5.0, 5.0])
-def test_free_squirmer_tilted(beta):
-    note("tilted free squirmer beta=%g" % beta)
+def test_free_squirmer_tilted(beta, layout):
+    note("tilted free squirmer beta=%g, %s" % (beta, layout))
     shape = (30, 26, 22)
     e = scenes.unit_vector(np.random.default_rng(11))
     body = dict(pos=(14.3, 12.9, 10.6), e=tuple(e), R=4.5, B1=2e-3, beta=beta)
-    o, s = make_pair(shape, [body])
+    o, s = make_pair(shape, [body], layout=layout)
     o.step(120)
     s.step(120)
     err, _ = rel_u_err(s, o)
@@ -165,14 +175,15 @@ def test_free_squirmer_tilted(beta):
     assert np.abs(s.body(0)["e"] - o.body(0)["e"]).max() < 1e-7
 
 
-def test_prescribed_motion_geometry_bit_exact():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_prescribed_motion_geometry_bit_exact(layout):
     """A prescribed body crosses many cells: owners and the full link set
     equal the oracle's bit for bit at every step; fields stay in tolerance."""
-    note("prescribed moving body, per-step link sets")
+    note("prescribed moving body, per-step link sets, %s" % layout)
     shape = (28, 24, 20)
     body = dict(pos=(9.2, 11.7, 10.1), e=(0, 1, 0), R=3.7, B1=5e-3, beta=2.0, mode="prescribed",
                 v=(0.23, 0.07, -0.05), w=(0.0, 0.01, 0.02))
-    o, s = make_pair(shape, [body])
+    o, s = make_pair(shape, [body], layout=layout)
     for t in range(25):
         o.step(1)
         s.step(1)
@@ -241,15 +252,16 @@ def test_many_bodies_fused_and_separate_update(nbody):
         check_bodies(s, o, bodies)
 
 
-def test_two_squirmers_with_contact():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_two_squirmers_with_contact(layout):
     """Two free squirmers swimming at each other reach WCA contact."""
-    note("two squirmers, WCA")
+    note("two squirmers, WCA, %s" % layout)
     shape = (40, 24, 24)
     bodies = [dict(pos=(13.0, 12.0, 12.0), e=(1, 0, 0), R=4.0, B1=0.03, beta=1.0),
               dict(pos=(23.5, 12.3, 12.1), e=(-1, 0.1, 0), R=4.0, B1=0.03, beta=-1.0)]
     lbsq = gpu()
     o = O.OracleSim(*shape, wca_sigma=1.0, wca_eps=0.01)
-    s = lbsq.Sim(shape, wca_sigma=1.0, wca_eps=0.01)
+    s = lbsq.Sim(shape, wca_sigma=1.0, wca_eps=0.01, layout=layout)
     for b in bodies:
         o.add_body(b["pos"], b["e"], b["R"], B1=b["B1"], beta=b["beta"])
         s.add_squirmer(b["pos"], b["e"], b["R"], B1=b["B1"], beta=b["beta"])
@@ -264,12 +276,13 @@ def test_two_squirmers_with_contact():
     assert wca_seen
 
 
-def test_tube_with_static_walls():
-    note("squirmer in a tube")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_tube_with_static_walls(layout):
+    note("squirmer in a tube, %s" % layout)
     shape = (24, 24, 40)
     mask = scenes.tube_mask(*shape, radius=9.0)
     body = dict(pos=(12.0, 12.0, 20.0), e=(0, 0, 1), R=4.0, B1=2e-3, beta=3.0)
-    o, s = make_pair(shape, [body], mask=mask)
+    o, s = make_pair(shape, [body], mask=mask, layout=layout)
     o.step(150)
     s.step(150)
     err, _ = rel_u_err(s, o)
@@ -306,14 +319,15 @@ def test_symmetric_placement_no_lateral_force():
     assert np.abs(T).max() < 1e-6 * 4.0 * abs(F[0])
 
 
-def test_poiseuille_body_force_hook():
-    note("Poiseuille (test body force)")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_poiseuille_body_force_hook(layout):
+    note("Poiseuille (test body force), %s" % layout)
     H, g = 8, 1e-4
     shape = (4, H + 2, 4)
     mask = np.zeros((4, H + 2, 4), np.uint8)
     mask[:, 0, :] = 1
     mask[:, H + 1, :] = 1
-    o, s = make_pair(shape, mask=mask, g=(g, 0.0, 0.0))
+    o, s = make_pair(shape, mask=mask, g=(g, 0.0, 0.0), layout=layout)
     n = int(40 / ((1 / 6) * (np.pi / H) ** 2))
     o.step(n)
     s.step(n)
@@ -325,18 +339,19 @@ def test_poiseuille_body_force_hook():
     assert np.abs(u[0, 0, 1:H + 1, 0] - exact).max() <= 1e-5 * exact.max()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("storage,saved_at", [("f32", 60), ("f32", 61), ("f16", 61)])
-def test_determinism_and_checkpoint_resume(storage, saved_at):
+def test_determinism_and_checkpoint_resume(storage, saved_at, layout):
     """Runs repeat bit for bit, and a state saved after an even or an odd
     number of steps (the two layouts of the in-place buffer) resumes to the
     same bits."""
-    note("determinism + checkpoint (%s, saved after %d steps)" % (storage, saved_at))
+    note("determinism + checkpoint (%s, saved after %d steps, %s)" % (storage, saved_at, layout))
     lbsq = gpu()
     shape = (32, 28, 24)
     specs = [((15.2, 13.9, 12.3), (0.6, 0.8, 0.0), 4.2, -2.0), ((4.1, 5.3, 6.2), (0.0, -0.6, 0.8), 3.1, 1.5)]
 
     def fresh():
-        s = lbsq.Sim(shape, storage=storage)
+        s = lbsq.Sim(shape, storage=storage, layout=layout)
         for pos, e, R, beta in specs:
             s.add_squirmer(pos, e, R, B1=0.01, beta=beta)
         return s
@@ -357,10 +372,11 @@ def test_determinism_and_checkpoint_resume(storage, saved_at):
             assert np.array_equal(a.body(i)[k], c.body(i)[k])
 
 
-def test_fused_audit_runs_and_flags_nothing():
-    note("fused audit")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_fused_audit_runs_and_flags_nothing(layout):
+    note("fused audit, %s" % layout)
     shape = (20, 20, 20)
-    o, s = make_pair(shape, [dict(pos=(10, 10, 10), R=4.0, B1=1e-3)], audit_every=5)
+    o, s = make_pair(shape, [dict(pos=(10, 10, 10), R=4.0, B1=1e-3)], audit_every=5, layout=layout)
     s.step(40)
     o.step(40)
     s.sync()
@@ -405,14 +421,15 @@ def test_error_paths():
     assert ei.value.code == lbsq.LB_ESTATE
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("storage,l2_tol", [("f16", 1e-3), ("bf16", 2e-2)])
-def test_reduced_precision_storage(storage, l2_tol):
+def test_reduced_precision_storage(storage, l2_tol, layout):
     """FP16 (scale 2^14) and BF16 deviation storage: velocity-field L2 error
     and swim velocity against the FP64 oracle."""
-    note("storage %s" % storage)
+    note("storage %s, %s" % (storage, layout))
     shape = (32, 32, 32)
     body = dict(pos=(16.0, 16.0, 16.0), e=(1, 0, 0), R=4.0, B1=1e-3, beta=-3.0)
-    o, s = make_pair(shape, [body], storage=storage)
+    o, s = make_pair(shape, [body], storage=storage, layout=layout)
     o.step(200)
     s.step(200)
     _, u, own = s.fields()

@@ -246,3 +246,31 @@ def test_server_isolates_a_diverging_request():
     assert results[1]["status"] == lbsq.LB_OK
     assert_same(results[1], alone(lbsq, good[0], good[1], good[2]), "request beside a diverging one")
     assert stats["arena_in_use"] == 0
+
+
+def test_step_batch_mixes_layouts():
+    """lb_step_batch over simulations in the in-place and the two-buffer
+    layout at once: each block takes its own simulation's layout, and every
+    result equals the same simulation stepped alone."""
+    note("lb_step_batch with both population layouts")
+    lbsq = gpu()
+    sel = [(REQUESTS[0], "ab"), (REQUESTS[1], "inplace"), (REQUESTS[5], "ab")]
+    sims = []
+    for (shape, bodies, _), layout in sel:
+        s = lbsq.Sim(shape, layout=layout)
+        for b in bodies:
+            s.add_squirmer(**b)
+        sims.append(s)
+    lbsq.step_batch(sims, 9)
+    lbsq.step_batch(sims, 14)
+    for ((shape, bodies, _), layout), s in zip(sel, sims):
+        ref = lbsq.Sim(shape, layout=layout)
+        for b in bodies:
+            ref.add_squirmer(**b)
+        ref.step(23)
+        assert np.array_equal(s.populations(), ref.populations()), layout
+        for i in range(len(bodies)):
+            for k in ("pos", "v", "w"):
+                assert np.array_equal(s.body(i)[k], ref.body(i)[k])
+        ref.close()
+        s.close()
