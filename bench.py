@@ -116,7 +116,7 @@ def run_gpu(storage, shape, R, beta, steps, warmup, layout="inplace"):
     }
 
 
-def serve(storage, reqs, arrivals, chunk, max_active, budget):
+def serve(storage, reqs, arrivals, chunk, max_active, budget, layout="inplace"):
     """Run the request stream through a server; arrivals None = all at once.
     Latency of a request = completion time - scheduled arrival."""
     import numpy as np
@@ -126,7 +126,8 @@ def serve(storage, reqs, arrivals, chunk, max_active, budget):
     if arrivals is None:
         arrivals = np.zeros(n)
     done = {}
-    with lbsq.Server(budget, max_active=max_active, chunk_steps=chunk, use_graph=True, storage=storage) as sv:
+    with lbsq.Server(budget, max_active=max_active, chunk_steps=chunk, use_graph=True, storage=storage,
+                     layout=layout) as sv:
         t0 = sv.clock()
         nxt = 0
         while len(done) < n:
@@ -161,7 +162,7 @@ def serve(storage, reqs, arrivals, chunk, max_active, budget):
             "chunks": stats["chunks"], "graphs": stats["graphs"], "speed": speed}
 
 
-def run_served(n_req, seed, chunk, max_active, budget_gb, storages):
+def run_served(n_req, seed, chunk, max_active, budget_gb, storages, layout="inplace"):
     """Capacity (all requests at once) in FP32, then each storage at a fixed
     Poisson rate of 0.6 x that capacity."""
     import numpy as np
@@ -169,17 +170,17 @@ def run_served(n_req, seed, chunk, max_active, budget_gb, storages):
     budget = int(budget_gb * (1 << 30))
     reqs = workloads.request_stream(n_req, seed=seed)
     warm = workloads.request_stream(2, seed=seed + 1, steps=50)
-    serve("f32", warm, None, chunk, max_active, budget)
-    cap = serve("f32", reqs, None, chunk, max_active, budget)
+    serve("f32", warm, None, chunk, max_active, budget, layout)
+    cap = serve("f32", reqs, None, chunk, max_active, budget, layout)
     qps = 0.6 * cap["req_per_s"]
     arrivals = workloads.poisson_arrivals(n_req, qps, seed=seed)
     out = {"workload": "Poisson stream of %d requests (seed %d): cubic boxes {48..192}^3, R {4,6,8,12}, "
                        "beta U[-5,5], B1 1e-3, 1000 steps, half single squirmers, half pairs" % (n_req, seed),
            "capacity_req_per_s": round(cap["req_per_s"], 2), "capacity_mlups": round(cap["mlups"], 1),
-           "qps": round(qps, 2), "chunk_steps": chunk, "max_active": max_active}
+           "qps": round(qps, 2), "chunk_steps": chunk, "max_active": max_active, "layout": layout}
     speeds = {}
     for st in storages:
-        r = serve(st, reqs, arrivals, chunk, max_active, budget)
+        r = serve(st, reqs, arrivals, chunk, max_active, budget, layout)
         speeds[st] = r.pop("speed")
         out[st] = {"mlups": round(r["mlups"], 1), "p50_ms": round(r["p50_ms"], 1), "p99_ms": round(r["p99_ms"], 1),
                    "req_per_s": round(r["req_per_s"], 2), "chunks": r["chunks"], "graphs": r["graphs"]}
@@ -232,6 +233,9 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=200)
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-layout", choices=["inplace", "ab"], default="ab",
+                    help="population layout of the served requests (the batch streams from HBM, where the "
+                         "two-buffer layout is faster)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -304,7 +308,8 @@ def main():
                                   "working_set_mb": round(2 * ws / 1e6, 1)}
     if not args.no_serve:
         out["served"] = run_served(args.serve_requests, args.serve_seed, args.serve_chunk, args.serve_active,
-                                   args.serve_budget_gb, ["f32"] if args.no_fp16 else ["f32", "f16"])
+                                   args.serve_budget_gb, ["f32"] if args.no_fp16 else ["f32", "f16"],
+                                   args.serve_layout)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(shape, args.R, args.beta, args.cpu_seconds)
     print(json.dumps(out), flush=True)

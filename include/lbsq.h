@@ -258,7 +258,10 @@ typedef struct lb_server lb_server;
  * storage, scale_log2, wca_sigma, wca_eps  as in lb_params, for every
  *               request (nu comes with each request, rho0 = 1, magic 3/16);
  * stream        hipStream_t of the batched steps (NULL: the server creates
- *               a non-blocking stream).                                   */
+ *               a non-blocking stream);
+ * layout        population layout of every request, as in lb_params (the
+ *               pull layout takes twice the population memory of each
+ *               request from the budget).                                 */
 typedef struct lb_server_params {
     size_t budget_bytes;
     int max_active;
@@ -267,6 +270,7 @@ typedef struct lb_server_params {
     int storage, scale_log2;
     double wca_sigma, wca_eps;
     void *stream;
+    int layout;
 } lb_server_params;
 
 /* One request: a periodic nx x ny x nz box at rest with viscosity nu and

@@ -118,14 +118,15 @@ void arena_free(void *p, void *ctx) { static_cast<lb_server *>(ctx)->arena.relea
 
 // Device bytes a request needs (each allocation of the handle rounded to
 // the arena granule), for rejecting requests that can never fit.
-size_t request_bytes(const lb_request *rq, int storage)
+size_t request_bytes(const lb_request *rq, int storage, int layout)
 {
     auto g = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
     const uint64_t n = uint64_t(rq->nx) * rq->ny * rq->nz;
     const uint64_t stride = ((n + 255) / 256) * 256 + 256;
     const size_t es = storage == LB_STORAGE_F32 ? 4 : 2;
     const uint64_t nblk = (n + BLOCK - 1) / BLOCK;
-    size_t t = g(size_t(Q) * stride * es) + 2 * g(n * sizeof(float)) + 2 * g(n) + 2 * g(MAXB * sizeof(DevBody));
+    const size_t npop = layout == LB_LAYOUT_AB ? 2 : 1;
+    size_t t = npop * g(size_t(Q) * stride * es) + 2 * g(n * sizeof(float)) + 2 * g(n) + 2 * g(MAXB * sizeof(DevBody));
     t += g(4 * (MAXB + 1) * sizeof(int)) + g(sizeof(SimDesc)) + g(NACCSET * ACCSET_SIZE * sizeof(unsigned long long));
     t += g(nblk * 5 * sizeof(double)) + g(8 * sizeof(double)) + g(4 * sizeof(int));
     return t;
@@ -172,6 +173,7 @@ struct GpuBackend {
         p.alloc = arena_alloc;
         p.free = arena_free;
         p.alloc_ctx = sv;
+        p.layout = sv->p.layout;
         lb_sim *s = nullptr;
         int rc = lb_create(&p, &s);
         for (int b = 0; rc == LB_OK && b < rq.nbody; ++b) {
@@ -379,7 +381,8 @@ int lb_server_create(const lb_server_params *p, lb_server **out)
     *out = nullptr;
     if (p->budget_bytes < (size_t(1) << 20) || p->max_active < 1 || p->max_active > LB_SERVER_MAXACTIVE ||
         p->chunk_steps < 1 || p->chunk_steps > 100000 || p->storage < 0 || p->storage > 2 || p->scale_log2 < 0 ||
-        p->scale_log2 > 20 || !(p->wca_sigma > 0.0) || p->wca_eps < 0.0)
+        p->scale_log2 > 20 || !(p->wca_sigma > 0.0) || p->wca_eps < 0.0 ||
+        (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB))
         return LB_EINVAL;
     static_assert(LB_SERVER_MAXACTIVE <= MAXSIM, "batch table too small");
     lb_server *sv = new (std::nothrow) lb_server();
@@ -424,7 +427,7 @@ int lb_server_submit(lb_server *sv, const lb_request *rq, uint64_t *ticket)
         rq->nbody > LB_REQ_MAXBODY || rq->nsteps < 0)
         return LB_EINVAL;
     if (uint64_t(rq->nx) * rq->ny * rq->nz >= (uint64_t(1) << 32)) return LB_EINVAL;
-    if (request_bytes(rq, sv->p.storage) > sv->p.budget_bytes) return LB_EBUDGET;
+    if (request_bytes(rq, sv->p.storage, sv->p.layout) > sv->p.budget_bytes) return LB_EBUDGET;
     return sv->core->submit(*rq, ticket);
 }
 

@@ -59,7 +59,8 @@ class LbSquirmer(C.Structure):
 class LbServerParams(C.Structure):
     _fields_ = [("budget_bytes", C.c_size_t), ("max_active", C.c_int), ("chunk_steps", C.c_int),
                 ("use_graph", C.c_int), ("storage", C.c_int), ("scale_log2", C.c_int),
-                ("wca_sigma", C.c_double), ("wca_eps", C.c_double), ("stream", C.c_void_p)]
+                ("wca_sigma", C.c_double), ("wca_eps", C.c_double), ("stream", C.c_void_p),
+                ("layout", C.c_int)]
 
 
 class LbRequest(C.Structure):
@@ -376,7 +377,7 @@ class Server:
     advanced together in batched chunks and retired with their results."""
 
     def __init__(self, budget_bytes, max_active=16, chunk_steps=100, use_graph=True, storage="f32",
-                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, stream=None):
+                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, stream=None, layout="inplace"):
         L = load()
         p = LbServerParams()
         p.budget_bytes = int(budget_bytes)
@@ -387,6 +388,7 @@ class Server:
         p.scale_log2 = int(14 if (scale_log2 is None and storage == "f16") else (scale_log2 or 0))
         p.wca_sigma, p.wca_eps = float(wca_sigma), float(wca_eps)
         p.stream = stream
+        p.layout = LAYOUT[layout]
         h = C.c_void_p()
         _check(L.lb_server_create(C.byref(p), C.byref(h)), "lb_server_create")
         self.h = h
