@@ -41,8 +41,8 @@ REQUESTS = [
 ]
 
 
-def alone(lbsq, shape, bodies, nsteps, storage="f32"):
-    s = lbsq.Sim(shape, storage=storage)
+def alone(lbsq, shape, bodies, nsteps, storage="f32", layout="inplace"):
+    s = lbsq.Sim(shape, storage=storage, layout=layout)
     for b in bodies:
         s.add_squirmer(**b)
     fluid0 = s.info()["n_fluid"]
@@ -106,12 +106,13 @@ def test_step_batch_rejects_repeated_handle():
     assert ei.value.code == lbsq.LB_EINVAL
 
 
-def run_server(lbsq, requests, storage="f32", use_graph=True, chunk=8, max_active=3, budget=None):
+def run_server(lbsq, requests, storage="f32", use_graph=True, chunk=8, max_active=3, budget=None,
+               layout="inplace"):
     if budget is None:
         budget = 1 << 30
     results = {}
     with lbsq.Server(budget, max_active=max_active, chunk_steps=chunk, use_graph=use_graph,
-                     storage=storage) as sv:
+                     storage=storage, layout=layout) as sv:
         tickets = {}
         # half the requests up front, the rest while the first ones run
         for j, (shape, bodies, n) in enumerate(requests[: len(requests) // 2]):
@@ -274,3 +275,17 @@ def test_step_batch_mixes_layouts():
                 assert np.array_equal(s.body(i)[k], ref.body(i)[k])
         ref.close()
         s.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_server_two_buffer_layout_matches_alone(storage):
+    """Requests served in the two-buffer pull layout equal the same
+    simulations stepped alone in that layout, bit for bit."""
+    note("server in the two-buffer layout, %s" % storage)
+    lbsq = gpu()
+    sel = REQUESTS[:4]
+    results, stats = run_server(lbsq, sel, storage=storage, chunk=16, max_active=3, layout="ab")
+    assert stats["arena_in_use"] == 0
+    for j, (shape, bodies, n) in enumerate(sel):
+        assert results[j]["status"] == lbsq.LB_OK
+        assert_same(results[j], alone(lbsq, shape, bodies, n, storage=storage, layout="ab"), "ab request %d" % j)
