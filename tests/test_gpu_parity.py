@@ -657,3 +657,29 @@ def test_largest_box_translation_invariance(storage, n):
         d = np.mod(a[6] - b[6], n)
         assert np.array_equal(d, np.array([0.0, 0.0, float(shift)])), d
         assert np.array_equal(a[7], b[7])
+
+
+def test_checkpoint_rejects_the_other_layout():
+    """A saved state records its population layout: restoring it into a
+    handle of the other layout is refused (the raw population bytes mean
+    different slots), into one of the same layout it resumes."""
+    lbsq = gpu()
+    note("checkpoint across layouts")
+    shape = (20, 18, 16)
+    a = lbsq.Sim(shape, layout="ab")
+    a.add_squirmer((9.3, 8.8, 7.9), (1, 0, 0), 3.5, B1=5e-3)
+    a.step(7)
+    blob = a.save_state()
+    b = lbsq.Sim(shape)
+    b.add_squirmer((9.3, 8.8, 7.9), (1, 0, 0), 3.5, B1=5e-3)
+    with pytest.raises(lbsq.LBError) as ei:
+        b.load_state(blob)
+    assert ei.value.code == lbsq.LB_EINVAL
+    c = lbsq.Sim(shape, layout="ab")
+    c.add_squirmer((9.3, 8.8, 7.9), (1, 0, 0), 3.5, B1=5e-3)
+    c.load_state(blob)
+    a.step(5)
+    c.step(5)
+    assert np.array_equal(a.populations(), c.populations())
+    for s in (a, b, c):
+        s.close()
