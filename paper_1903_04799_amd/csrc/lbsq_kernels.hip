@@ -4,8 +4,10 @@
 // A time step t is two launches on one stream, each covering every
 // simulation of a batch (one simulation is a batch of one):
 //   k_fluid           every fluid cell, in place on one population buffer
-//                     (the AA pattern described below), FP32 arithmetic on
-//                     stored deviations, non-temporal stores.  Its leading blocks
+//                     (the AA pattern described below) or, per simulation,
+//                     pulling from one of two buffers into the other; FP32
+//                     arithmetic on stored deviations, non-temporal stores.
+//                     Its leading blocks
 //                     take the cells next to a body, found in the bodies'
 //                     boxes, one thread per (cell, direction): pull streaming
 //                     and the TRT collision of eq. (lb) with moving-wall
@@ -315,6 +317,11 @@ __device__ __forceinline__ float collide_one(const StepArgs &a, const float *f, 
 // Bounce-back from a solid source s = x - c_i takes the cell's own f*_ibar(x),
 // which sits in F[ibar][s] before an even step and in F[i][x] before an odd
 // one; neither slot is written by anyone else in the step.
+//
+// Pull streaming on two buffers (chosen per simulation): step t reads buffer
+// A = t & 1 and writes the other, B:
+//   f_i^in(x) = A[i][x - c_i] (A[ibar][x] from a solid source);
+//   f*_i(x) -> B[i][x].
 
 // Element idx of a population plane P, addressed by a 32-bit byte offset from
 // the plane's (uniform) base: the loads and stores then take the scalar-base,
@@ -1249,8 +1256,8 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
 }
 
 // Population i of every cell as FP64 (solid cells read 0), and back.  Each
-// (i, cell) pair owns one slot of the in-place layout, so these are
-// permutations of the buffer.
+// (i, cell) pair owns one slot of the buffer in either layout, so these are
+// permutations of it.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_plane_to_f64(StepArgs a, const typename S::T *__restrict__ A,
                                                         const uint8_t *__restrict__ own, int lay, int i,
