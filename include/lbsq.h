@@ -63,7 +63,7 @@ enum {
 enum { LB_STORAGE_F32 = 0, LB_STORAGE_F16 = 1, LB_STORAGE_BF16 = 2 };
 enum { LB_FREE = 0, LB_FIXED = 1, LB_PRESCRIBED = 2 };
 enum { LB_OWNER_FLUID = 0, LB_OWNER_WALL = 255 }; /* bodies: id + 1 */
-enum { LB_LAYOUT_INPLACE = 0, LB_LAYOUT_AB = 1 };
+enum { LB_LAYOUT_INPLACE = 0, LB_LAYOUT_AB = 1, LB_LAYOUT_AUTO = 2 };
 
 typedef void *(*lb_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*lb_free_fn)(void *ptr, void *ctx);
@@ -94,8 +94,12 @@ typedef void (*lb_free_fn)(void *ptr, void *ctx);
  *                faster form while the buffer fits the 256 MB last-level
  *                cache); LB_LAYOUT_AB (1): two buffers, each step pulls
  *                from one and writes the other (the faster form for boxes
- *                whose populations stream from HBM).  Results agree to
- *                round-off; the checkpoint format is the same.            */
+ *                whose populations stream from HBM); LB_LAYOUT_AUTO (2):
+ *                the pull layout for boxes of more than 5,500,000 cells
+ *                (about 176^3), in place below (measured on MI355X: in
+ *                place wins at 160^3 and below, pull from 192^3 up).
+ *                Results agree to round-off.  A saved state records the
+ *                layout and restores only into a handle of the same one. */
 typedef struct lb_params {
     int nx, ny, nz;
     double nu, magic, rho0;

@@ -270,6 +270,9 @@ int mirror_owner(lb_sim *s)
 // whether the last completed step had an even index (the in-place layout)
 bool after_even(const lb_sim *s) { return (s->steps & 1) == 1; }
 
+// cells above which LB_LAYOUT_AUTO takes the two-buffer pull layout
+constexpr uint64_t AUTO_PULL_CELLS = 5500000;
+
 // The buffer holding the populations after the steps taken so far, and its
 // layout: in place the one buffer, by the parity of the last step; in the
 // pull layout the buffer the last step wrote (buffer steps & 1).
@@ -373,11 +376,15 @@ int lb_create(const lb_params *p, lb_sim **out)
     // one population plane must stay below 4 GiB (32-bit offsets in the kernels)
     if (plane_stride(n) * (p->storage == LB_STORAGE_F32 ? 4 : 2) > (uint64_t(1) << 32)) return LB_EINVAL;
     if ((p->alloc == nullptr) != (p->free == nullptr)) return LB_EINVAL;
-    if (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB) return LB_EINVAL;
+    if (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB && p->layout != LB_LAYOUT_AUTO)
+        return LB_EINVAL;
 
     lb_sim *s = new (std::nothrow) lb_sim();
     if (!s) return LB_ENOMEM;
     s->p = *p;
+    // the pull layout above the measured crossover (in place wins at 160^3
+    // and below, pull from 192^3 up, in FP32 and FP16 alike)
+    if (s->p.layout == LB_LAYOUT_AUTO) s->p.layout = n > AUTO_PULL_CELLS ? LB_LAYOUT_AB : LB_LAYOUT_INPLACE;
     (void)hipGetDevice(&s->device);
     s->stream = static_cast<hipStream_t>(p->stream);
     Box &bx = s->args.box;
@@ -414,7 +421,7 @@ int lb_create(const lb_params *p, lb_sim **out)
 
     const size_t fbytes = size_t(Q) * bx.stride * s->esize;
     s->f = dev_alloc(s, fbytes);
-    if (p->layout == LB_LAYOUT_AB) s->f2 = dev_alloc(s, fbytes);
+    if (s->p.layout == LB_LAYOUT_AB) s->f2 = dev_alloc(s, fbytes);
     for (int k = 0; k < 2; ++k) {
         s->d_dens[k] = static_cast<float *>(dev_alloc(s, size_t(n) * sizeof(float)));
         s->own[k] = static_cast<uint8_t *>(dev_alloc(s, n));
@@ -427,7 +434,7 @@ int lb_create(const lb_params *p, lb_sim **out)
     s->d_audit_out = static_cast<double *>(dev_alloc(s, 8 * sizeof(double)));
     s->d_err = static_cast<int *>(dev_alloc(s, NERR * sizeof(int)));
     s->d_desc = static_cast<SimDesc *>(dev_alloc(s, sizeof(SimDesc)));
-    if (!s->f || (p->layout == LB_LAYOUT_AB && !s->f2) || !s->d_dens[0] || !s->d_dens[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
+    if (!s->f || (s->p.layout == LB_LAYOUT_AB && !s->f2) || !s->d_dens[0] || !s->d_dens[1] || !s->own[0] || !s->own[1] || !s->d_bodies[0] || !s->d_bodies[1] ||
         !s->d_lists || !s->d_acc || !s->d_audit_part || !s->d_audit_out || !s->d_err || !s->d_desc) {
         lb_destroy(s);
         return LB_ENOMEM;

@@ -21,7 +21,7 @@ LIB_PATH = Path(__file__).resolve().parent / "liblbsq.so"
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EGEOM, LB_ESTATE, LB_ENAN, LB_EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 LB_ECANCELED = -8
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
-LAYOUT = {"inplace": 0, "ab": 1}
+LAYOUT = {"inplace": 0, "ab": 1, "auto": 2}
 MODES = {"free": 0, "fixed": 1, "prescribed": 2}
 Q = 19
 

@@ -683,3 +683,50 @@ def test_checkpoint_rejects_the_other_layout():
     assert np.array_equal(a.populations(), c.populations())
     for s in (a, b, c):
         s.close()
+
+
+def test_layouts_agree_bit_for_bit():
+    """Both population layouts do the same arithmetic on the same values
+    (only the slots differ), so a scene with walls, a free squirmer and a
+    prescribed body converting cells gives bit-identical populations, body
+    states and forces in both."""
+    lbsq = gpu()
+    note("in-place and pull layouts, bit for bit")
+    shape = (30, 26, 28)
+    mask = scenes.tube_mask(*shape, radius=12.0)
+    out = []
+    for layout in LAYOUTS:
+        s = lbsq.Sim(shape, layout=layout)
+        s.set_static_mask(mask)
+        s.add_squirmer((14.3, 12.9, 10.6), (0.3, 0.2, 0.93), 3.5, B1=0.02, beta=-2.0)
+        s.add_squirmer((15.1, 13.4, 20.2), (0, 0, 1), 3.0, B1=5e-3, mode="prescribed", v=(0.0, 0.04, 0.17))
+        s.step(33)
+        st = [s.body(i) for i in range(2)]
+        ft = [s.force_torque(i) for i in range(2)]
+        out.append((s.populations(), st, ft))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for i in range(2):
+        for k in ("pos", "e", "v", "w"):
+            assert np.array_equal(out[0][1][i][k], out[1][1][i][k])
+        assert np.array_equal(out[0][2][i][0], out[1][2][i][0]) and np.array_equal(out[0][2][i][1], out[1][2][i][1])
+
+
+def test_automatic_layout_follows_the_box_size():
+    """LB_LAYOUT_AUTO resolves to in place for a small box and to the pull
+    layout above 5,500,000 cells; a saved state shows which (it restores
+    only into a handle of the same layout)."""
+    lbsq = gpu()
+    note("automatic layout: 24^3 and 180^3")
+    for n, resolved, other in ((24, "inplace", "ab"), (180, "ab", "inplace")):
+        a = lbsq.Sim((n, n, n), layout="auto")
+        a.step(3)
+        blob = a.save_state()
+        same = lbsq.Sim((n, n, n), layout=resolved)
+        same.load_state(blob)
+        diff = lbsq.Sim((n, n, n), layout=other)
+        with pytest.raises(lbsq.LBError) as ei:
+            diff.load_state(blob)
+        assert ei.value.code == lbsq.LB_EINVAL
+        for s in (a, same, diff):
+            s.close()
