@@ -618,8 +618,9 @@ def test_kernel_timing_changes_no_result():
         assert np.array_equal(out[0][2][k], out[1][2][k])
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("storage,n", [("f32", 1023), ("f16", 1290)])
-def test_largest_box_translation_invariance(storage, n):
+def test_largest_box_translation_invariance(storage, n, layout):
     """The largest cubic box the 32-bit plane offsets allow (1023^3 in FP32,
     1290^3 in FP16, 92-103 GB on the device). A prescribed squirmer
     straddling the periodic z boundary, so that it touches the highest
@@ -630,13 +631,13 @@ def test_largest_box_translation_invariance(storage, n):
     agree bit for bit after every step."""
     import torch
     lbsq = gpu()
-    note("largest box %d^3 %s: translation invariance at the highest offsets" % (n, storage))
+    note("largest box %d^3 %s %s: translation invariance at the highest offsets" % (n, storage, layout))
     z_top, z_low = n - 1.625, 20.375  # the first straddles the periodic z boundary
     shift = n - 22  # = z_top - z_low, whole cells
     v, w = (2.0 ** -10, 0.0, 2.0 ** -11), (0.0, 0.0, 2.0 ** -12)
     runs = []
     for z in (z_top, z_low):
-        s = lbsq.Sim((n, n, n), storage=storage)
+        s = lbsq.Sim((n, n, n), storage=storage, layout=layout)
         s.add_squirmer((n / 2 + 0.25, n / 2 - 0.125, z), (0.6, 0.8, 0.0), 6.0, B1=1e-3, beta=2.0,
                        mode="prescribed", v=v, w=w)
         out = []
