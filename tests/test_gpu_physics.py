@@ -291,6 +291,53 @@ def test_E5_neutral_squirmer_oscillates_in_a_tube():
     assert 0.2 * travel < z_at_xmax < 0.8 * travel
 
 
+@pytest.mark.parametrize("layout", ["inplace", "ab"])
+def test_near_field_scene_long_run(layout):
+    """The near-field scene at its real size over a long run: a 256^3
+    periodic box, a fixed no-slip sphere A = 32 at the centre, and a pusher
+    (beta = -3, R = 16) heading at it with an impact parameter drawn from the
+    seed, 16 cells from its surface.  Over 20,000 steps (Sec. "Scattering off
+    and Orbiting around a Stationary Spherical Obstacle" runs this set-up far
+    longer):
+    - the swimmer closes in on the obstacle at a speed of order v0, and the
+      two never overlap;
+    - every body state stays finite and the swimmer stays slow (|v| < 10 v0);
+    - the mean fluid density moves by under 1e-5 relative, while the fluid
+      cell count changes as the swimmer crosses the lattice."""
+    from tests import scenes
+    lbsq = gpu()
+    sc = scenes.obstacle_scene(0)
+    note("near-field scene 256^3, b=%.3f, 20000 steps, %s layout" % (sc["b"], layout))
+    s = lbsq.Sim((256, 256, 256), layout=layout)
+    s.add_squirmer(sc["obstacle"], (1.0, 0.0, 0.0), sc["A"], mode="fixed")
+    s.add_squirmer(sc["squirmer"], (1.0, 0.0, 0.0), sc["R"], B1=B1, beta=-3.0)
+    centre = np.array(sc["obstacle"])
+
+    def gap():
+        return float(np.linalg.norm(s.body(1)["pos"] - centre)) - sc["A"] - sc["R"]
+
+    m0, _ = s.audit()
+    n0 = s.info()["n_fluid"]
+    g0, x0 = gap(), float(s.body(1)["pos"][0])
+    gaps = []
+    for _ in range(10):
+        s.step(2000)
+        b = s.body(1)
+        assert all(np.isfinite(b[k]).all() for k in ("pos", "v", "e", "w"))
+        assert np.linalg.norm(b["v"]) < 10.0 * V0
+        gaps.append(gap())
+    m1, _ = s.audit()
+    n1 = s.info()["n_fluid"]
+    x1 = float(s.body(1)["pos"][0])
+    s.close()
+    drho = (m1 / n1) / (m0 / n0) - 1.0
+    note("  gap %.2f -> %.2f (min %.2f), x advanced %.2f cells, fluid cells %+d, mean density %+.2e"
+         % (g0, gaps[-1], min(gaps), x1 - x0, n1 - n0, drho))
+    assert min(gaps) > 0.0
+    assert gaps[-1] < g0 and x1 - x0 > 0.3 * V0 * 20000
+    assert abs(drho) < 1e-5
+
+
 def _stripe_amplitude(s, L):
     """Mean alternating part of u_x / v0 along the swimming axis through the
     body: |u_i - (u_{i-1} + u_{i+1}) / 2| over runs of three fluid cells."""
