@@ -132,3 +132,24 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_traffic_summary_matches_the_kernel_sources():
+    """The committed counter summary of the fluid kernel at 128^3, R = 8 was
+    taken on the kernel sources as they stand (its hash matches), and its
+    bytes per launch lie within 5% above the algorithmic traffic: 152 B per
+    update in FP32 and 76 B in FP16, times the scene's 2,094,976 fluid cells
+    (the pull of every population and the write of every post-collision
+    value of the update eq. (lb), per cell)."""
+    import importlib.util
+    root = Path(__file__).resolve().parents[1]
+    spec = importlib.util.spec_from_file_location("bench_for_test", root / "bench.py")
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    fluid = 2094976
+    for storage in ("f32", "f16"):
+        t = bench.measured_traffic(storage, (128, 128, 128), 8.0)
+        assert t is not None, "profiles/k_fluid_128cube_traffic.md predates the kernel sources"
+        algo = bench.BYTES_PER_UPDATE[storage] * fluid
+        assert algo <= t <= 1.05 * algo, (storage, t, algo)
+    assert bench.measured_traffic("f32", (256, 256, 256), 16.0) is None
