@@ -732,6 +732,19 @@ static void one_step(or_sim *s)
     convert_cells(s);
 }
 
+/* Test-only: the cell conversion of eq. (consforce) alone, on the state the
+ * caller has written.  The owners still describe the bodies where they were
+ * when the populations were set; the caller has moved the bodies since
+ * (or_set_body_state).  Covered and uncovered cells are converted exactly
+ * as at the end of a step, and the conversion force and torque are left in
+ * Fc_next, Tc_next.  No streaming, collision or integration takes place. */
+int or_convert_only(or_sim *s)
+{
+    s->geom_error = 0;
+    convert_cells(s);
+    return s->geom_error ? -2 : 0;
+}
+
 int or_step(or_sim *s, int nsteps)
 {
     for (int t = 0; t < nsteps && !s->runaway; ++t) one_step(s);

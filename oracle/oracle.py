@@ -54,6 +54,7 @@ def lib():
         L.or_add_body.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                   dp, dp, C.c_double]
         L.or_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_convert_only.argtypes = [C.c_void_p]
         L.or_get_fields.argtypes = [C.c_void_p, dp, dp, C.c_void_p]
         L.or_get_populations.argtypes = [C.c_void_p, dp]
         L.or_set_populations.argtypes = [C.c_void_p, dp]
@@ -192,6 +193,14 @@ class OracleSim:
 
     def step(self, n=1):
         rc = lib().or_step(self.h, int(n))
+        if rc:
+            raise RuntimeError("oracle: geometry error (%d)" % rc)
+
+    def convert_only(self):
+        """Test-only: convert the cells the bodies covered or uncovered since
+        the owners were last computed (after ``set_body``), eq. (consforce),
+        with nothing else of a step."""
+        rc = lib().or_convert_only(self.h)
         if rc:
             raise RuntimeError("oracle: geometry error (%d)" % rc)
 

@@ -579,3 +579,108 @@ def test_P11_swim_speed_matches_paper_R4():
     # the instantaneous speed fluctuates by about 1%: 3% separates the
     # readings by a factor of four
     assert abs(mean / ref - 1.0) < 0.03, (mean, ref)
+
+
+# --------------------------------------------------------------------------
+# P15: cell conversion alone (Sec. "Numerical Method", the refill and
+# zeroing of converted cells and eq. (consforce)), recomputed here from the
+# text with no oracle arithmetic.  A prescribed body that translates and
+# rotates is moved by a fraction of a cell on a random fluid state, and one
+# conversion is run.  Expected, cell by cell:
+#   - covered cells (fluid before, body now) hand the momentum sum_i c_i f_i
+#     to the body, F_c += p and T_c += d x p, with d the lever arm from the
+#     body centre to the cell centre; their populations become zero;
+#   - uncovered cells (body before, fluid now) are refilled with the
+#     equilibrium at the mean density of their D3Q19 neighbours that are fluid
+#     at both time levels (rho0 if there are none) and at the rigid-body
+#     velocity v + w x d without the squirmer slip, and the body gives up that
+#     momentum: F_c -= rho u, T_c -= d x rho u;
+#   - every other fluid cell keeps its populations.
+# A sign of either torque term, the order of either cross product, the
+# neighbour set or the refill velocity, taken otherwise, misses by orders of
+# magnitude more than the tolerance.
+def _feq_text(c, w, rho, u):
+    cu = c @ u
+    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * float(u @ u))
+
+
+def _lever_to(shape, pos, x, y, z):
+    d = np.array([x + 0.5, y + 0.5, z + 0.5]) - np.asarray(pos, dtype=float)
+    L = np.asarray(shape, dtype=float)
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_P15_conversion_force_torque_and_refill(case):
+    shape = [(14, 13, 12), (16, 14, 15), (13, 15, 14)][case]
+    rng = np.random.default_rng(1500 + case)
+    nx, ny, nz = shape
+    R = [3.6, 4.2, 3.3][case]
+    pos0 = np.array(shape, dtype=float) / 2.0 + rng.uniform(-0.5, 0.5, 3)
+    e = rng.standard_normal(3)
+    e /= np.linalg.norm(e)
+    v = rng.uniform(-0.05, 0.05, 3)
+    w = rng.uniform(-0.04, 0.04, 3)
+    step = rng.uniform(0.35, 0.6, 3) * rng.choice([-1.0, 1.0], 3)
+    pos1 = pos0 + step
+    B1, beta = 0.02, -3.0
+
+    o = O.OracleSim(*shape)
+    o.add_body(pos0, e, R, B1=B1, beta=beta, mode=O.PRESCRIBED, v=v, w=w)
+    c, wt = O.lattice()
+    # random fluid state: density 1 +- 5%, velocity up to 0.05, plus noise
+    rho_f = 1.0 + 0.05 * rng.standard_normal((nz, ny, nx))
+    u_f = 0.05 * rng.standard_normal((3, nz, ny, nx))
+    cu = np.einsum("ia,azyx->izyx", c.astype(float), u_f)
+    f = wt[:, None, None, None] * rho_f * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (u_f ** 2).sum(0))
+    f += 1e-3 * rng.standard_normal(f.shape)
+    o.set_populations(f)
+    f_before = o.populations().copy()  # zero inside the body at pos0
+
+    o.set_body(0, pos1, e, v, w)
+    o.convert_only()
+    b = o.body(0)
+    f_after = o.populations()
+
+    own0 = exact_owner(shape, [(pos0, R)])
+    own1 = exact_owner(shape, [(pos1, R)])
+    covered = (own0 == 0) & (own1 != 0)
+    uncovered = (own0 != 0) & (own1 == 0)
+    stay = (own0 == 0) & (own1 == 0)
+    assert covered.sum() >= 10 and uncovered.sum() >= 10
+
+    Fc = np.zeros(3)
+    Tc = np.zeros(3)
+    expect = np.zeros_like(f_before)
+    expect[:, stay] = f_before[:, stay]
+    for z, y, x in zip(*np.nonzero(covered)):
+        p = np.array([sum(c[i][a] * f_before[i, z, y, x] for i in range(19)) for a in range(3)])
+        d = _lever_to(shape, pos1, x, y, z)
+        Fc += p
+        Tc += np.array([d[1] * p[2] - d[2] * p[1], d[2] * p[0] - d[0] * p[2],
+                        d[0] * p[1] - d[1] * p[0]])
+    for z, y, x in zip(*np.nonzero(uncovered)):
+        dens = []
+        for i in range(1, 19):
+            xx, yy, zz = (x + c[i][0]) % nx, (y + c[i][1]) % ny, (z + c[i][2]) % nz
+            if stay[zz, yy, xx]:
+                dens.append(f_before[:, zz, yy, xx].sum())
+        rho_bar = sum(dens) / len(dens) if dens else 1.0
+        d = _lever_to(shape, pos1, x, y, z)
+        u = v + np.array([w[1] * d[2] - w[2] * d[1], w[2] * d[0] - w[0] * d[2],
+                          w[0] * d[1] - w[1] * d[0]])
+        expect[:, z, y, x] = _feq_text(c.astype(float), wt, rho_bar, u)
+        p = rho_bar * u
+        Fc -= p
+        Tc -= np.array([d[1] * p[2] - d[2] * p[1], d[2] * p[0] - d[0] * p[2],
+                        d[0] * p[1] - d[1] * p[0]])
+
+    # covered and uncovered momenta are each ~0.05 per cell; their sums and
+    # lever-arm products are O(1), so FP64 reordering gives ~1e-15
+    assert np.abs(b["Fc_next"] - Fc).max() < 1e-14 * max(1.0, np.abs(Fc).max())
+    assert np.abs(b["Tc_next"] - Tc).max() < 1e-14 * max(1.0, np.abs(Tc).max() * R)
+    assert np.abs(f_after - expect).max() < 1e-15
+    # the torque is not degenerate: a flipped sign or swapped product moves
+    # it by far more than the tolerance
+    assert np.abs(Tc).max() > 1e-3
+    o.close()
