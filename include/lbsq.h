@@ -177,6 +177,19 @@ int lb_sync(lb_sim *s);
  * g: (sum f c - g/2)/rho, the half-step velocity).                          */
 int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner);
 
+/* For callers that cannot allocate device memory (code around HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * readout as lb_read_fields, same arguments, layout and results (bit for
+ * bit), with no device allocation and no call of the handle's allocator.
+ * The fields pass through a fixed 16 MiB device array per GPU, held until
+ * the process ends, in chunks of 508,160 cells; any box size is read.
+ * Every call on one GPU shares that array: calls from several threads are
+ * serialised by a per-device lock (overlapping calls would race on it), and
+ * each returns only after its last copy out of the array has ended.
+ * LB_EINVAL for a NULL handle, rho or u; LB_EDEVICE if the array's device
+ * address cannot be obtained or a launch or copy fails.                     */
+int lb_read_fields_noalloc(lb_sim *s, double *rho, double *u, uint8_t *owner);
+
 /* Hydrodynamic force and torque on body id from the last completed step:
  * momentum exchange eqs. (bbforce), (bbtorque) plus conversion eq.
  * (consforce).  These are the values the integrator used, minus WCA.       */

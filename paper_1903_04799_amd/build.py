@@ -9,7 +9,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "liblbsq.so"
-SOURCES = ["lbsq_kernels.hip", "lbsq_api.hip", "lbsq_serve.hip"]
+SOURCES = ["lbsq_kernels.hip", "lbsq_api.hip", "lbsq_serve.hip", "lbsq_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

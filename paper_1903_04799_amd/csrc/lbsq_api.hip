@@ -300,6 +300,9 @@ int classify_now(lb_sim *s)
 }  // namespace
 
 void *lbsq_dev_alloc(lb_sim *s, size_t bytes) { return dev_alloc(s, bytes); }
+int lbsq_sync_check(lb_sim *s) { return sync_check(s); }
+const void *lbsq_pop_buf(const lb_sim *s) { return pop_buf(s); }
+int lbsq_pop_lay(const lb_sim *s) { return pop_lay(s); }
 void lbsq_dev_free(lb_sim *s, void *p) { dev_free(s, p); }
 
 // Owner flags of the current buffer computed if pending; the handle counts
@@ -447,7 +450,7 @@ int lb_create(const lb_params *p, lb_sim **out)
     if (e == hipSuccess) e = hipMemsetAsync(s->own[1], 0, n, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_err, 0, NERR * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess || upload_desc(s) != LB_OK) {
+    if (e != hipSuccess || upload_desc(s) != LB_OK || lbsq_noalloc_init(s->device) != LB_OK) {
         lb_destroy(s);
         return LB_EDEVICE;
     }
@@ -584,7 +587,8 @@ int lb_read_fields(lb_sim *s, double *rho, double *u, uint8_t *owner)
     uint8_t *d_o = static_cast<uint8_t *>(dev_alloc(s, n));
     int rc = LB_OK;
     if (!d_rho || !d_u || !d_o) rc = LB_ENOMEM;
-    if (rc == LB_OK && launch_fields(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), d_rho, d_u, d_o, s->stream) !=
+    if (rc == LB_OK && launch_fields(s->p.storage, s->args, pop_buf(s), s->own[s->cur], pop_lay(s), 0, n, d_rho, d_u, d_o,
+                                         s->stream) !=
                            hipSuccess)
         rc = LB_EDEVICE;
     if (rc == LB_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = LB_EDEVICE;

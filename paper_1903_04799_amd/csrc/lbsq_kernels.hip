@@ -1227,17 +1227,19 @@ __global__ __launch_bounds__(BLOCK) void k_audit_final(const double *__restrict_
 
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::T *__restrict__ A,
-                                                  const uint8_t *__restrict__ own, int lay,
-                                                  double *__restrict__ rho, double *__restrict__ u,
-                                                  uint8_t *__restrict__ own_out)
+                                                  const uint8_t *__restrict__ own, int lay, uint32_t c0,
+                                                  uint32_t cnt, double *__restrict__ rho,
+                                                  double *__restrict__ u, uint8_t *__restrict__ own_out)
 {
-    const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= a.box.n) return;
+    // cells [c0, c0 + cnt) into slots 0..cnt-1; u holds three planes of cnt
+    const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= cnt) return;
+    const uint32_t c = c0 + q;
     const uint8_t o = own[c];
-    own_out[c] = is_fluid(o) ? 0 : o;
+    own_out[q] = is_fluid(o) ? 0 : o;
     if (!is_fluid(o)) {
-        rho[c] = 0.0;
-        u[c] = u[a.box.n + c] = u[2 * size_t(a.box.n) + c] = 0.0;
+        rho[q] = 0.0;
+        u[q] = u[cnt + q] = u[2 * size_t(cnt) + q] = 0.0;
         return;
     }
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -1251,8 +1253,8 @@ __global__ __launch_bounds__(BLOCK) void k_fields(StepArgs a, const typename S::
         j[2] += cz(i) * v;
     }
     r += a.rho0d;
-    rho[c] = r;
-    for (int k = 0; k < 3; ++k) u[k * size_t(a.box.n) + c] = (j[k] - 0.5 * double(a.g[k])) / r;
+    rho[q] = r;
+    for (int k = 0; k < 3; ++k) u[k * size_t(cnt) + q] = (j[k] - 0.5 * double(a.g[k])) / r;
 }
 
 // Population i of every cell as FP64 (solid cells read 0), and back.  Each
@@ -1409,21 +1411,22 @@ hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uin
 }
 
 template <class S>
-static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, int lay, double *rho,
-                                  double *u, uint8_t *own_out, hipStream_t s)
+static hipError_t launch_fields_t(const StepArgs &a, const void *A, const uint8_t *own, int lay, uint32_t c0,
+                                  uint32_t cnt, double *rho, double *u, uint8_t *own_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fields<S>, dim3((a.box.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
-                       static_cast<const typename S::T *>(A), own, lay, rho, u, own_out);
+    if (cnt == 0 || c0 > a.box.n || cnt > a.box.n - c0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fields<S>, dim3((cnt + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a,
+                       static_cast<const typename S::T *>(A), own, lay, c0, cnt, rho, u, own_out);
     return hipGetLastError();
 }
 
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
-                         double *rho, double *u, uint8_t *own_out, hipStream_t s)
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay, uint32_t c0,
+                         uint32_t cnt, double *rho, double *u, uint8_t *own_out, hipStream_t s)
 {
     switch (storage) {
-    case 1: return launch_fields_t<StF16>(a, A, own, lay, rho, u, own_out, s);
-    case 2: return launch_fields_t<StBF16>(a, A, own, lay, rho, u, own_out, s);
-    default: return launch_fields_t<StF32>(a, A, own, lay, rho, u, own_out, s);
+    case 1: return launch_fields_t<StF16>(a, A, own, lay, c0, cnt, rho, u, own_out, s);
+    case 2: return launch_fields_t<StBF16>(a, A, own, lay, c0, cnt, rho, u, own_out, s);
+    default: return launch_fields_t<StF32>(a, A, own, lay, c0, cnt, rho, u, own_out, s);
     }
 }
 

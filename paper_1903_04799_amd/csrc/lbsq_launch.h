@@ -104,8 +104,9 @@ hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int si
 // even step; LAY_AB: the buffer the last step of the pull layout wrote).
 hipError_t launch_audit(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
                         double *part, double *out, int *err, hipStream_t s);
-hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay,
-                         double *rho, double *u, uint8_t *own_out, hipStream_t s);
+// Fields of cells [c0, c0 + cnt) into rho[cnt], u[3][cnt] and own_out[cnt].
+hipError_t launch_fields(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay, uint32_t c0,
+                         uint32_t cnt, double *rho, double *u, uint8_t *own_out, hipStream_t s);
 hipError_t launch_plane(int storage, const StepArgs &a, void *A, const uint8_t *own, int lay, int i,
                         double *buf, int to_f64, hipStream_t s);
 hipError_t launch_dens(int storage, const StepArgs &a, const void *A, const uint8_t *own, int lay, float *dens,

@@ -65,3 +65,12 @@ int lbsq_prepare(lb_sim *s);
 // Device memory through the handle's allocator.
 void *lbsq_dev_alloc(lb_sim *s, size_t bytes);
 void lbsq_dev_free(lb_sim *s, void *p);
+// Stream synchronised and device error flags turned into a status.
+int lbsq_sync_check(lb_sim *s);
+// The buffer holding the populations after the steps taken so far, and its
+// layout (LAY_*), for the readout kernels.
+const void *lbsq_pop_buf(const lb_sim *s);
+int lbsq_pop_lay(const lb_sim *s);
+// Device address of this GPU's no-allocation scratch array, looked up once
+// per device with that device current (lbsq_noalloc.hip).
+int lbsq_noalloc_init(int device);

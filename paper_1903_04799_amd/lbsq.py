@@ -32,6 +32,7 @@ EXPORTED = [
     "lb_save_state", "lb_load_state", "lb_kernel_timing", "lb_kernel_time", "lb_destroy",
     "lb_strerror", "lb_server_create", "lb_server_submit", "lb_server_progress", "lb_server_results",
     "lb_server_stats_get", "lb_server_clock", "lb_server_destroy", "lb_server_cancel",
+    "lb_read_fields_noalloc",
 ]
 LB_REQ_MAXBODY = 8
 LB_SERVER_MAXACTIVE = 64
@@ -119,6 +120,7 @@ def load():
         "lb_step_batch": [C.POINTER(vp), ip, ip],
         "lb_sync": [vp],
         "lb_read_fields": [vp, dp, dp, vp],
+        "lb_read_fields_noalloc": [vp, dp, dp, vp],
         "lb_force_torque": [vp, ip, dp, dp],
         "lb_force_parts": [vp, ip, dp, dp, dp, dp],
         "lb_body_state": [vp, ip, dp, dp, dp, dp, dp],
@@ -173,10 +175,12 @@ class _TorchMemory:
         self.torch = torch
         self.device = device
         self.blocks = {}
+        self.nalloc = 0  # allocator calls made by the library so far
         self.alloc_cb = ALLOC_FN(self._alloc)
         self.free_cb = FREE_FN(self._free)
 
     def _alloc(self, nbytes, ctx):
+        self.nalloc += 1
         try:
             t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
         except Exception:
@@ -290,6 +294,17 @@ class Sim:
         u = np.empty(3 * self.n)
         own = np.empty(self.n, dtype=np.uint8)
         _check(load().lb_read_fields(self.h, _dptr(rho), _dptr(u), own.ctypes.data), "lb_read_fields")
+        return rho.reshape(nz, ny, nx), u.reshape(3, nz, ny, nx), own.reshape(nz, ny, nx)
+
+    def fields_noalloc(self):
+        """The same as ``fields()`` through lb_read_fields_noalloc, which
+        allocates no device memory."""
+        nx, ny, nz = self.shape
+        rho = np.empty(self.n)
+        u = np.empty(3 * self.n)
+        own = np.empty(self.n, dtype=np.uint8)
+        _check(load().lb_read_fields_noalloc(self.h, _dptr(rho), _dptr(u), own.ctypes.data),
+               "lb_read_fields_noalloc")
         return rho.reshape(nz, ny, nx), u.reshape(3, nz, ny, nx), own.reshape(nz, ny, nx)
 
     def force_torque(self, i=0):
