@@ -63,7 +63,7 @@ enum {
 enum { LB_STORAGE_F32 = 0, LB_STORAGE_F16 = 1, LB_STORAGE_BF16 = 2 };
 enum { LB_FREE = 0, LB_FIXED = 1, LB_PRESCRIBED = 2 };
 enum { LB_OWNER_FLUID = 0, LB_OWNER_WALL = 255 }; /* bodies: id + 1 */
-enum { LB_LAYOUT_INPLACE = 0, LB_LAYOUT_AB = 1, LB_LAYOUT_AUTO = 2 };
+enum { LB_LAYOUT_AUTO = 0, LB_LAYOUT_INPLACE = 1, LB_LAYOUT_AB = 2 };
 
 typedef void *(*lb_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*lb_free_fn)(void *ptr, void *ctx);
@@ -89,17 +89,18 @@ typedef void (*lb_free_fn)(void *ptr, void *ctx);
  *                the collision every this many steps (0 = never);
  *   stream       hipStream_t to run on (NULL = the null stream);
  *   alloc, free, alloc_ctx  optional device allocator pair;
- *   layout       LB_LAYOUT_INPLACE (0): one population buffer, each step
+ *   layout       LB_LAYOUT_AUTO (0, the default of a zeroed struct): the
+ *                pull layout for boxes of more than 5,500,000 cells (about
+ *                176^3), in place below (measured on MI355X: in place wins
+ *                at 160^3 and below, pull from 192^3 up);
+ *                LB_LAYOUT_INPLACE (1): one population buffer, each step
  *                reads and rewrites it in place (half the memory; the
  *                faster form while the buffer fits the 256 MB last-level
- *                cache); LB_LAYOUT_AB (1): two buffers, each step pulls
+ *                cache); LB_LAYOUT_AB (2): two buffers, each step pulls
  *                from one and writes the other (the faster form for boxes
- *                whose populations stream from HBM); LB_LAYOUT_AUTO (2):
- *                the pull layout for boxes of more than 5,500,000 cells
- *                (about 176^3), in place below (measured on MI355X: in
- *                place wins at 160^3 and below, pull from 192^3 up).
- *                Results agree to round-off.  A saved state records the
- *                layout and restores only into a handle of the same one. */
+ *                whose populations stream from HBM).  Results agree bit
+ *                for bit.  A saved state records the resolved layout and
+ *                restores only into a handle of the same one. */
 typedef struct lb_params {
     int nx, ny, nz;
     double nu, magic, rho0;
@@ -276,9 +277,11 @@ typedef struct lb_server lb_server;
  *               request (nu comes with each request, rho0 = 1, magic 3/16);
  * stream        hipStream_t of the batched steps (NULL: the server creates
  *               a non-blocking stream);
- * layout        population layout of every request, as in lb_params (the
- *               pull layout takes twice the population memory of each
- *               request from the budget).                                 */
+ * layout        population layout of every request: LB_LAYOUT_INPLACE or
+ *               LB_LAYOUT_AB as in lb_params; LB_LAYOUT_AUTO (0) takes the
+ *               pull layout, since a batch of resident requests streams
+ *               from HBM (the pull layout takes twice the population memory
+ *               of each request from the budget).                         */
 typedef struct lb_server_params {
     size_t budget_bytes;
     int max_active;

@@ -63,6 +63,9 @@
  * Couette pin.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -905,3 +908,23 @@ void or_audit(const or_sim *s, double *mass, double *P)
 }
 
 long or_get_step(const or_sim *s) { return s->step; }
+
+/* OpenMP threads the stream/collide loop runs on, and a way to set them
+ * (the CPU baseline times the oracle on all host threads and on one). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

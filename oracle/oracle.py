@@ -69,6 +69,9 @@ def lib():
         L.or_get_step.restype = C.c_long
         L.or_get_step.argtypes = [C.c_void_p]
         L.or_relaxation_rates.argtypes = [C.c_void_p, dp, dp]
+        L.or_threads.restype = C.c_int
+        L.or_threads.argtypes = []
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_lattice.argtypes = [C.POINTER(C.c_int), dp]
         L.or_feq.argtypes = [C.c_double, dp, dp]
         L.or_slip.argtypes = [dp, dp, C.c_double, C.c_double, dp]
@@ -86,6 +89,15 @@ def lib():
 def _d(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def threads():
+    """OpenMP threads the oracle's stream/collide loop uses."""
+    return int(lib().or_threads())
+
+
+def set_threads(n):
+    lib().or_set_threads(int(n))
 
 
 def lattice():

@@ -788,7 +788,9 @@ struct StateHeader {
     int32_t pad;
 };
 
-static constexpr uint64_t STATE_MAGIC = 0x34717362'6c62ull;
+// the saved-state format; the last byte is its version (2: layout codes
+// with LB_LAYOUT_AUTO = 0)
+static constexpr uint64_t STATE_MAGIC = 0x34717362'6c02ull;
 static constexpr size_t ACC_BYTES = NACCSET * ACCSET_SIZE * sizeof(unsigned long long);
 
 int lb_state_size(lb_sim *s, size_t *bytes)

@@ -382,12 +382,15 @@ int lb_server_create(const lb_server_params *p, lb_server **out)
     if (p->budget_bytes < (size_t(1) << 20) || p->max_active < 1 || p->max_active > LB_SERVER_MAXACTIVE ||
         p->chunk_steps < 1 || p->chunk_steps > 100000 || p->storage < 0 || p->storage > 2 || p->scale_log2 < 0 ||
         p->scale_log2 > 20 || !(p->wca_sigma > 0.0) || p->wca_eps < 0.0 ||
-        (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB))
+        (p->layout != LB_LAYOUT_INPLACE && p->layout != LB_LAYOUT_AB && p->layout != LB_LAYOUT_AUTO))
         return LB_EINVAL;
     static_assert(LB_SERVER_MAXACTIVE <= MAXSIM, "batch table too small");
     lb_server *sv = new (std::nothrow) lb_server();
     if (!sv) return LB_ENOMEM;
     sv->p = *p;
+    // a batch of resident requests streams from HBM, where the pull layout
+    // is the faster one
+    if (sv->p.layout == LB_LAYOUT_AUTO) sv->p.layout = LB_LAYOUT_AB;
     sv->t0 = std::chrono::steady_clock::now();
     (void)hipGetDevice(&sv->device);
     int rc = LB_OK;

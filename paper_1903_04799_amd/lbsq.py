@@ -21,7 +21,7 @@ LIB_PATH = Path(__file__).resolve().parent / "liblbsq.so"
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EGEOM, LB_ESTATE, LB_ENAN, LB_EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 LB_ECANCELED = -8
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
-LAYOUT = {"inplace": 0, "ab": 1, "auto": 2}
+LAYOUT = {"auto": 0, "inplace": 1, "ab": 2}
 MODES = {"free": 0, "fixed": 1, "prescribed": 2}
 Q = 19
 
@@ -218,7 +218,7 @@ class Sim:
 
     def __init__(self, shape, nu=1.0 / 6.0, magic=3.0 / 16.0, rho0=1.0, storage="f32",
                  scale_log2=None, wca_sigma=1.0, wca_eps=0.01, g=(0.0, 0.0, 0.0), audit_every=0,
-                 stream=None, torch_memory=True, layout="inplace"):
+                 stream=None, torch_memory=True, layout="auto"):
         L = load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -392,7 +392,7 @@ class Server:
     advanced together in batched chunks and retired with their results."""
 
     def __init__(self, budget_bytes, max_active=16, chunk_steps=100, use_graph=True, storage="f32",
-                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, stream=None, layout="inplace"):
+                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, stream=None, layout="auto"):
         L = load()
         p = LbServerParams()
         p.budget_bytes = int(budget_bytes)

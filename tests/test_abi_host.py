@@ -134,22 +134,46 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_summary_matches_the_kernel_sources():
-    """The committed counter summary of the fluid kernel at 128^3, R = 8 was
-    taken on the kernel sources as they stand (its hash matches), and its
-    bytes per launch lie within 5% above the algorithmic traffic: 152 B per
-    update in FP32 and 76 B in FP16, times the scene's 2,094,976 fluid cells
-    (the pull of every population and the write of every post-collision
-    value of the update eq. (lb), per cell)."""
+def _bench():
     import importlib.util
     root = Path(__file__).resolve().parents[1]
     spec = importlib.util.spec_from_file_location("bench_for_test", root / "bench.py")
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    fluid = 2094976
-    for storage in ("f32", "f16"):
-        t = bench.measured_traffic(storage, (128, 128, 128), 8.0)
-        assert t is not None, "profiles/k_fluid_128cube_traffic.md predates the kernel sources"
-        algo = bench.BYTES_PER_UPDATE[storage] * fluid
-        assert algo <= t <= 1.05 * algo, (storage, t, algo)
-    assert bench.measured_traffic("f32", (256, 256, 256), 16.0) is None
+    return bench
+
+
+def test_profile_summaries_match_the_kernel_sources():
+    """The committed rocprofv3 summaries of the fluid kernel at 256^3, R = 16
+    (the HBM-bound figure of bench.py's roofline) were taken on the kernel
+    sources as they stand (their hash matches), and their figures are
+    consistent:
+    - the counter traffic per launch lies within 5% above the algorithmic
+      bytes, 152 B per update in FP32 and 76 B in FP16 times the scene's
+      16,760,056 fluid cells (the pull of every population and the write of
+      every post-collision value of the update eq. (lb), per cell);
+    - the kernel-trace averages give at most the 8 TB/s HBM peak and at least
+      60% of it."""
+    bench = _bench()
+    fluid = 16760056
+    for lay in ("ab", "inplace"):
+        for storage in ("f32", "f16"):
+            t = bench.profiled(bench.TRAFFIC_256, "traffic_bytes_per_launch_%s_%s" % (storage, lay))
+            assert t is not None, "profiles/k_fluid_256cube_traffic.md predates the kernel sources"
+            algo = bench.BYTES_PER_UPDATE[storage] * fluid
+            assert algo <= t <= 1.05 * algo, (storage, lay, t, algo)
+            us = bench.profiled(bench.TRACE_256, "k_fluid_us_%s_%s" % (storage, lay))
+            assert us is not None, "profiles/k_fluid_256cube_kernel_trace.md predates the kernel sources"
+            gbs = algo / (us * 1e-6) / 1e9
+            assert 0.6 * bench.HBM_PEAK_GBS <= gbs <= bench.HBM_PEAK_GBS, (storage, lay, gbs)
+
+
+def test_profile_figures_are_ignored_once_the_kernels_change(tmp_path):
+    """A summary whose hash does not match the kernel sources gives no
+    figures (bench.py then reports null rather than a stale number)."""
+    bench = _bench()
+    p = tmp_path / "summary.md"
+    p.write_text("sources_sha256_16 = 0000000000000000\nk_fluid_us_f32_ab = 1.0\n")
+    assert bench.profiled(p, "k_fluid_us_f32_ab") is None
+    p.write_text("sources_sha256_16 = %s\nk_fluid_us_f32_ab = 1.0\n" % bench.kernel_sources_hash())
+    assert bench.profiled(p, "k_fluid_us_f32_ab") == 1.0
