@@ -396,6 +396,13 @@ int lb_create(const lb_params *p, lb_sim **out)
     bx.nz = p->nz;
     bx.n = uint32_t(n);
     bx.stride = plane_stride(n);
+    // tiled populations wherever the step kernels' 32-bit byte offsets reach
+    // the whole buffer (up to 56.5 million cells in FP32, 113 million in
+    // the half-width forms); planes beyond
+    const uint64_t esz = p->storage == LB_STORAGE_F32 ? 4 : 2;
+    const bool tiled = (n + 255) / 256 * 256 * Q * esz <= (uint64_t(1) << 32);
+    bx.dstride = tiled ? 256 : bx.stride;
+    bx.tmul = tiled ? uint32_t(Q - 1) * 256 : 0;
     magic_divisor(uint32_t(p->nx), bx.mx, bx.sx);
     magic_divisor(uint32_t(p->ny), bx.my, bx.sy);
     s->args.lam_e = float(le);
@@ -788,9 +795,10 @@ struct StateHeader {
     int32_t pad;
 };
 
-// the saved-state format; the last byte is its version (2: layout codes
-// with LB_LAYOUT_AUTO = 0)
-static constexpr uint64_t STATE_MAGIC = 0x34717362'6c02ull;
+// the saved-state format; the last byte is its version (3: populations in
+// tiles of 256 cells where they fit 32-bit offsets, layout codes with
+// LB_LAYOUT_AUTO = 0)
+static constexpr uint64_t STATE_MAGIC = 0x34717362'6c03ull;
 static constexpr size_t ACC_BYTES = NACCSET * ACCSET_SIZE * sizeof(unsigned long long);
 
 int lb_state_size(lb_sim *s, size_t *bytes)

@@ -200,13 +200,32 @@ __device__ __forceinline__ int wrap_small(int a, int n)
 struct Box {
     int nx, ny, nz;
     uint32_t n;       // cells
-    uint64_t stride;  // elements between population planes
+    uint64_t stride;  // elements between population planes (buffer size / 19)
+    // Where population i of cell c sits in a buffer: i * dstride + c +
+    // (c >> 8) * tmul (see pop_slot).
+    uint64_t dstride;
+    uint32_t tmul;
     // division by nx and ny as a multiply and shift, exact for dividends
     // below 2^31: q = umulhi(v, m) >> s
     uint32_t mx, sx, my, sy;
 };
 
 __device__ __forceinline__ uint32_t div_magic(uint32_t v, uint32_t m, uint32_t s) { return __umulhi(v, m) >> s; }
+
+// Population layout within a buffer.  Tiled (tmul = 18 * 256, dstride =
+// 256): the cells form groups of 256 consecutive cells, and the 19
+// directions of a group are stored one after another, 256 elements each, so
+// group g starts at element g * 19 * 256.  A block of 256 cells then writes
+// one contiguous run of 19 * 256 elements and reads from a handful of
+// neighbouring runs.  Planes (tmul = 0, dstride = stride): direction i is
+// one plane; taken where a tiled buffer would outgrow the 32-bit byte
+// offsets of the step kernels.  pop_off is the part that depends on the
+// cell (it fits 32 bits in either form); pop_slot the whole index.
+__host__ __device__ __forceinline__ uint32_t pop_off(const Box &b, uint32_t c) { return c + (c >> 8) * b.tmul; }
+__host__ __device__ __forceinline__ uint64_t pop_slot(const Box &b, int i, uint32_t c)
+{
+    return uint64_t(i) * b.dstride + pop_off(b, c);
+}
 
 // Minimum image of a real difference in a box of length L (|d| < 1.5 L).
 __device__ __forceinline__ double min_image(double d, int L)

@@ -333,6 +333,15 @@ __device__ __forceinline__ float ld_plane(gptr<const typename S::T> P, uint32_t 
     using T = typename S::T;
     return S::dec(*(gptr<const T>)((gptr<const char>)P + idx * uint32_t(sizeof(T))));
 }
+// The same load, non-temporal: the pull layout reads each population once
+// per step and never rewrites the lines it reads, so they need not stay in
+// the caches.
+template <class S>
+__device__ __forceinline__ float ld_plane_nt(gptr<const typename S::T> P, uint32_t idx)
+{
+    using T = typename S::T;
+    return S::dec(__builtin_nontemporal_load((gptr<const T>)((gptr<const char>)P + idx * uint32_t(sizeof(T)))));
+}
 template <class S>
 __device__ __forceinline__ void st_plane_nt(gptr<typename S::T> P, uint32_t idx, float v)
 {
@@ -363,10 +372,10 @@ struct Planes {
 // layout (LAY_AB).
 __device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y, int z, int lay)
 {
-    if (lay == LAY_AB) return uint64_t(j) * bx.stride + cell_of(bx, x, y, z);
-    if (lay == LAY_AA_EVEN) return uint64_t(opp(j)) * bx.stride + cell_of(bx, x, y, z);
-    return uint64_t(j) * bx.stride + cell_of(bx, wrap_small(x + rcx(j), bx.nx), wrap_small(y + rcy(j), bx.ny),
-                                             wrap_small(z + rcz(j), bx.nz));
+    if (lay == LAY_AB) return pop_slot(bx, j, cell_of(bx, x, y, z));
+    if (lay == LAY_AA_EVEN) return pop_slot(bx, opp(j), cell_of(bx, x, y, z));
+    return pop_slot(bx, j, cell_of(bx, wrap_small(x + rcx(j), bx.nx), wrap_small(y + rcy(j), bx.ny),
+                                wrap_small(z + rcz(j), bx.nz)));
 }
 
 // ---------------------------------------------------------------------------
@@ -379,19 +388,21 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
 {
     // F is the buffer read (and, in place, written); the pull layout writes
     // the other buffer, to_write bytes away
-    const Planes<typename S::T> P(F, a.box.stride);
+    const Box &bx = a.box;
+    const Planes<typename S::T> P(F, bx.dstride);
     const uint32_t idx = blk * BLOCK + threadIdx.x;
-    const uint8_t o = idx < a.box.n ? own[idx] : OWN_WALL;
+    const uint8_t o = idx < bx.n ? own[idx] : OWN_WALL;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (o == OWN_FLUID || o == OWN_NB_WALL) {
-        const Nbr nb(a.box, idx);
+        const Nbr nb(bx, idx);
+        const uint32_t oi = pop_off(bx, idx);
         float f[Q];
         if (o == OWN_FLUID) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if (MODE == STEP_AA_ODD) f[i] = ld_plane<S>(P.p[opp(i)], nb.src(i));
-                else if (MODE == STEP_AB) f[i] = ld_plane<S>(P.p[i], nb.src(i));
-                else f[i] = ld_plane<S>(P.p[i], idx);
+                if (MODE == STEP_AA_ODD) f[i] = ld_plane<S>(P.p[opp(i)], pop_off(bx, nb.src(i)));
+                else if (MODE == STEP_AB) f[i] = ld_plane_nt<S>(P.p[i], pop_off(bx, nb.src(i)));
+                else f[i] = ld_plane<S>(P.p[i], oi);
             }
         } else {
             // no-slip walls: a population that would come from a wall is the
@@ -400,19 +411,19 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
             for (int i = 0; i < Q; ++i) {
                 const uint32_t s = nb.src(i);
                 const bool fl = is_fluid(own[s]);
-                if (MODE == STEP_AB) f[i] = fl ? ld_plane<S>(P.p[i], s) : ld_plane<S>(P.p[opp(i)], idx);
-                else if ((MODE == STEP_AA_ODD) == fl) f[i] = ld_plane<S>(P.p[opp(i)], s);
-                else f[i] = ld_plane<S>(P.p[i], idx);
+                if (MODE == STEP_AB) f[i] = fl ? ld_plane_nt<S>(P.p[i], pop_off(bx, s)) : ld_plane_nt<S>(P.p[opp(i)], oi);
+                else if ((MODE == STEP_AA_ODD) == fl) f[i] = ld_plane<S>(P.p[opp(i)], pop_off(bx, s));
+                else f[i] = ld_plane<S>(P.p[i], oi);
             }
         }
         float out[Q];
         collide<S, FORCE>(a, f, out);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            if (MODE == STEP_AA_ODD) st_plane_nt<S>(P.p[i], nb.src(opp(i)), out[i]);
+            if (MODE == STEP_AA_ODD) st_plane_nt<S>(P.p[i], pop_off(bx, nb.src(opp(i))), out[i]);
             else if (MODE == STEP_AB)
-                st_plane_nt<S>((gptr<typename S::T>)((gptr<char>)P.p[i] + to_write), idx, out[i]);
-            else st_plane_nt<S>(P.p[opp(i)], idx, out[i]);
+                st_plane_nt<S>((gptr<typename S::T>)((gptr<char>)P.p[i] + to_write), oi, out[i]);
+            else st_plane_nt<S>(P.p[opp(i)], oi, out[i]);
         }
         if (AUDIT) audit_add<S>(a, out, am);
     }
@@ -700,7 +711,6 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     __shared__ float s_f[CPB][Q + 1], s_o[CPB][Q + 1];
     __shared__ int s_minb[CPB];
     const Box &bx = a.box;
-    const uint64_t st = bx.stride;
     // the block's body and first shell cell (precomputed), the thread's
     // (shell cell, direction)
     const int4 bi = blkinfo[blk];
@@ -742,11 +752,11 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
     if (valid) {
         constexpr bool ODD = MODE == STEP_AA_ODD;
         if (MODE == STEP_AB) {
-            f_in = S::ld(F[i * st + s], a.inv_scale);
-            f_ref = S::ld(F[opp(i) * st + c], a.inv_scale);
+            f_in = S::ld(F[pop_slot(bx, i, s)], a.inv_scale);
+            f_ref = S::ld(F[pop_slot(bx, opp(i), c)], a.inv_scale);
         } else {
-            f_in = S::ld(F[ODD ? opp(i) * st + s : i * st + c], a.inv_scale);
-            f_ref = S::ld(F[ODD ? i * st + c : opp(i) * st + s], a.inv_scale);
+            f_in = S::ld(F[ODD ? pop_slot(bx, opp(i), s) : pop_slot(bx, i, c)], a.inv_scale);
+            f_ref = S::ld(F[ODD ? pop_slot(bx, i, c) : pop_slot(bx, opp(i), s)], a.inv_scale);
         }
         dprev = dens_prev[c];
     }
@@ -785,14 +795,14 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, gptr<typename 
         const typename S::T o = S::st(collide_one<FORCE>(a, s_f[cl], i), a.scale);
         s_o[cl][i] = S::ld(o, a.inv_scale);
         if (MODE == STEP_AA_ODD) {
-            const uint64_t at = i * st + cell_of(bx, wrap_small(x + rcx(i), bx.nx), wrap_small(y + rcy(i), bx.ny),
-                                                 wrap_small(z + rcz(i), bx.nz));
+            const uint64_t at = pop_slot(bx, i, cell_of(bx, wrap_small(x + rcx(i), bx.nx),
+                                                        wrap_small(y + rcy(i), bx.ny), wrap_small(z + rcz(i), bx.nz)));
             __builtin_nontemporal_store(o, &F[at]);
         } else if (MODE == STEP_AB) {
             const gptr<typename S::T> W = (gptr<typename S::T>)((gptr<char>)F + to_write);
-            __builtin_nontemporal_store(o, &W[i * st + c]);
+            __builtin_nontemporal_store(o, &W[pop_slot(bx, i, c)]);
         } else {
-            __builtin_nontemporal_store(o, &F[opp(i) * st + c]);
+            __builtin_nontemporal_store(o, &F[pop_slot(bx, opp(i), c)]);
         }
     }
     __syncthreads();

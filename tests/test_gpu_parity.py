@@ -585,10 +585,13 @@ def test_kernel_timing_changes_no_result():
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("storage,n", [("f32", 1023), ("f16", 1290)])
+@pytest.mark.parametrize("storage,n", [("f32", 1023), ("f16", 1290), ("f32", 383), ("f16", 483)])
 def test_largest_box_translation_invariance(storage, n, layout):
-    """The largest cubic box the 32-bit plane offsets allow (1023^3 in FP32,
-    1290^3 in FP16, 92-103 GB on the device). A prescribed squirmer
+    """The largest cubic boxes of each population form: 1023^3 in FP32 and
+    1290^3 in FP16 (92-103 GB on the device), the largest the 32-bit offsets
+    of population planes allow; 383^3 in FP32 and 483^3 in FP16, the
+    largest whose tiled populations (19 directions per group of 256 cells)
+    fit 32-bit offsets. A prescribed squirmer
     straddling the periodic z boundary, so that it touches the highest
     offsets, must see exactly the forces of the same squirmer shifted by an
     integer number of cells to the low planes. Positions, velocities and
