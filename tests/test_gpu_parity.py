@@ -377,6 +377,42 @@ def test_determinism_and_checkpoint_resume(storage, saved_at, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("saved_at", [40, 41])
+def test_checkpoint_with_static_walls(saved_at, layout):
+    """A state with static walls (a tube) saved after an even or odd step
+    resumes bit for bit in a fresh handle that was never given the wall
+    mask: the walls travel with the saved owners, and the streaming path's
+    per-cell wall masks are rebuilt from them."""
+    note("checkpoint with static walls (saved after %d steps, %s)" % (saved_at, layout))
+    lbsq = gpu()
+    shape = (30, 26, 28)
+    mask = scenes.tube_mask(*shape, radius=11.0)
+
+    def fresh(walls=True):
+        s = lbsq.Sim(shape, layout=layout)
+        if walls:
+            s.set_static_mask(mask)
+        s.add_squirmer((14.3, 12.9, 10.6), (0.3, 0.2, 0.93), 3.5, B1=0.02, beta=-2.0)
+        return s
+
+    a = fresh()
+    a.step(saved_at)
+    blob = a.save_state()
+    a.step(50)
+    c = fresh(walls=False)
+    c.load_state(blob)
+    c.step(50)
+    assert np.array_equal(a.populations(), c.populations())
+    for k in ("pos", "e", "v", "w"):
+        assert np.array_equal(a.body(0)[k], c.body(0)[k])
+    _, _, own_a = a.fields()
+    _, _, own_c = c.fields()
+    assert np.array_equal(own_a, own_c) and (own_a == 255).sum() == mask.sum()
+    a.close()
+    c.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_fused_audit_runs_and_flags_nothing(layout):
     note("fused audit, %s" % layout)
     shape = (20, 20, 20)
@@ -387,6 +423,26 @@ def test_fused_audit_runs_and_flags_nothing(layout):
     m_g, P_g = s.audit()
     m_o, P_o = o.audit()
     assert abs(m_g - m_o) <= 1e-9 * m_o and np.abs(P_g - P_o).max() <= 1e-5 * np.abs(P_o).max()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_audit_changes_no_result(storage, layout):
+    """The fused audit (every 100 steps by default in the binding) only
+    reads: a run audited every 7 steps ends bit for bit where an unaudited
+    one does, populations, owners and bodies."""
+    note("audit changes no result (%s, %s)" % (storage, layout))
+    lbsq = gpu()
+    out = []
+    for every in (0, 7):
+        s = lbsq.Sim((30, 26, 22), storage=storage, layout=layout, audit_every=every)
+        s.add_squirmer((14.3, 12.9, 10.6), (0.6, 0.8, 0.0), 4.5, B1=5e-3, beta=-3.0)
+        s.step(100)
+        out.append((s.populations(), s.fields()[2], s.body(0)))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for k in ("pos", "e", "v", "w"):
+        assert np.array_equal(out[0][2][k], out[1][2][k])
 
 
 def test_nan_is_reported():
