@@ -1,0 +1,117 @@
+"""Scattering off, or orbiting around, a fixed spherical obstacle (Sec.
+"Scattering off and Orbiting around a Stationary Spherical Obstacle").
+
+A squirmer of radius R starts a surface gap g0 away from a fixed no-slip
+sphere of radius A and swims toward its centre along a heading turned by a
+small angle off the radial direction (the symmetry breaking the paper
+describes).  The run is classified as
+
+  - ``orbit``: the swimmer revolves more than halfway around the obstacle
+    (the swept angle of its position about the obstacle's centre exceeds
+    180 degrees), the paper's criterion;
+  - ``scatter``: after contact (surface gap below ``contact_gap``) it
+    leaves again, the gap rising above ``release_gap``;
+  - ``no contact``: the run ends without contact (the swimmer is held off
+    or turned away before it reaches the obstacle);
+  - ``undecided``: contact, but neither of the above within the run.
+
+The motion stays in the plane spanned by the start position and the
+heading (the z = centre plane), so the swept angle is measured there.
+`bisect` brackets the critical beta between an orbiting and a scattering
+value, as the paper does once one of each is known.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import lbsq
+
+
+def classify(gaps, angles, contact_gap=1.5, release_gap=16.0):
+    """Outcome of a run from its sampled surface gaps and unwrapped swept
+    angles (radians, from the start).  Returns (outcome, index) with the
+    sample index at which it was decided (or the last one)."""
+    touched = None
+    for k, (g, a) in enumerate(zip(gaps, angles)):
+        if abs(a) > math.pi:
+            return "orbit", k
+        if touched is None and g < contact_gap:
+            touched = k
+        if touched is not None and g > release_gap:
+            return "scatter", k
+    if touched is None:
+        return "no contact", len(gaps) - 1
+    return "undecided", len(gaps) - 1
+
+
+def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, max_steps=600000,
+              every=2000, storage="f16", layout="auto", contact_gap=1.5, release_gap=16.0, log=None):
+    """One run; stops as soon as the outcome is decided.  Returns a dict with
+    the outcome, the step it was decided at, and the sampled trajectory
+    (step, surface gap, swept angle in degrees, heading angle to the
+    obstacle centre in degrees)."""
+    c = np.array([n / 2.0, n / 2.0, n / 2.0])
+    d0 = A + R + gap0
+    start = c - np.array([d0, 0.0, 0.0])
+    th = math.radians(angle_deg)
+    e = (math.cos(th), math.sin(th), 0.0)
+    s = lbsq.Sim((n, n, n), storage=storage, layout=layout)
+    s.add_squirmer(tuple(c), (1.0, 0.0, 0.0), A, B1=0.0, mode="fixed")
+    s.add_squirmer(tuple(start), e, R, B1=B1, beta=beta)
+    phi0 = math.atan2(start[1] - c[1], start[0] - c[0])
+    prev, unwrap = phi0, 0.0
+    rows, gaps, angles = [], [], []
+    t0 = time.time()
+    outcome, k = "undecided", 0
+    steps = 0
+    try:
+        while steps < max_steps:
+            s.step(every)
+            steps += every
+            b = s.body(1)
+            r = b["pos"] - c
+            r -= n * np.round(r / n)
+            dist = float(np.linalg.norm(r))
+            phi = math.atan2(r[1], r[0])
+            dphi = phi - prev
+            dphi -= 2.0 * math.pi * round(dphi / (2.0 * math.pi))
+            unwrap += dphi
+            prev = phi
+            heading = math.degrees(math.acos(max(-1.0, min(1.0, float(-np.dot(r, b["e"]) / dist)))))
+            gap = dist - A - R
+            gaps.append(gap)
+            angles.append(unwrap)
+            rows.append((steps, gap, math.degrees(unwrap), heading))
+            if log is not None and (steps // every) % 25 == 0:
+                log("  beta %g step %d: gap %.2f, swept %.1f deg, heading %.1f deg off the centre (%.0f s)"
+                    % (beta, steps, gap, math.degrees(unwrap), heading, time.time() - t0))
+            outcome, k = classify(gaps, angles, contact_gap, release_gap)
+            if outcome in ("orbit", "scatter"):
+                break
+    finally:
+        s.close()
+    return {"beta": beta, "outcome": outcome, "decided_at": rows[k][0] if rows else 0, "steps": steps,
+            "min_gap": float(min(gaps)) if gaps else None,
+            "max_swept_deg": float(max(abs(a) for a in angles) * 180.0 / math.pi) if angles else 0.0,
+            "trajectory": rows, "A": A, "R": R, "n": n, "B1": B1, "gap0": gap0, "angle_deg": angle_deg,
+            "storage": storage, "seconds": time.time() - t0}
+
+
+def bisect(beta_orbit, beta_scatter, tol=1.0, run=orbit_run, **kw):
+    """Bracket the critical beta between a value known to orbit and one known
+    to scatter (or not to orbit), halving the bracket until it is narrower
+    than tol.  Returns the bracket and every run made."""
+    lo, hi = float(beta_orbit), float(beta_scatter)
+    runs = []
+    while abs(hi - lo) > tol:
+        mid = 0.5 * (lo + hi)
+        r = run(mid, **kw)
+        runs.append(r)
+        if r["outcome"] == "orbit":
+            lo = mid
+        else:
+            hi = mid
+    return (lo, hi), runs

@@ -1,0 +1,39 @@
+"""The orbit/scatter driver's bookkeeping (CPU): the classification of a
+sampled trajectory by the paper's criterion (Sec. "Scattering off and
+Orbiting around a Stationary Spherical Obstacle": an orbit revolves more
+than halfway around the obstacle) and the bisection over beta, on
+synthetic trajectories and a fake run.  The GPU runs themselves are
+recorded in the design notes."""
+import math
+
+from paper_1903_04799_amd import orbit
+
+
+def test_orbit_needs_more_than_half_a_revolution():
+    gaps = [10.0, 3.0, 1.0, 1.1, 1.0, 1.2]
+    angles = [0.0, 0.2, 1.0, 2.0, 3.0, 3.0]
+    assert orbit.classify(gaps, angles)[0] == "undecided"
+    angles[-1] = math.pi + 0.01
+    assert orbit.classify(gaps, angles) == ("orbit", 5)
+    # either sense of revolution counts
+    assert orbit.classify(gaps, [-a for a in angles]) == ("orbit", 5)
+
+
+def test_scatter_needs_contact_then_release():
+    # leaving without ever touching is not a scattering off the obstacle
+    assert orbit.classify([10.0, 12.0, 30.0], [0.0, 0.1, 0.2])[0] == "no contact"
+    out = orbit.classify([10.0, 1.0, 5.0, 17.0], [0.0, 0.3, 0.5, 0.6])
+    assert out == ("scatter", 3)
+    # a release before contact does not count
+    assert orbit.classify([20.0, 1.2, 1.0], [0.0, 0.1, 0.2])[0] == "undecided"
+
+
+def test_bisection_brackets_the_critical_beta():
+    critical = -33.3
+
+    def fake(beta, **kw):
+        return {"beta": beta, "outcome": "orbit" if beta < critical else "scatter"}
+
+    (lo, hi), runs = orbit.bisect(-50.0, -20.0, tol=1.0, run=fake)
+    assert lo <= critical <= hi and hi - lo <= 1.0
+    assert all(r["outcome"] == ("orbit" if r["beta"] < critical else "scatter") for r in runs)
