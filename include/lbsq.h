@@ -86,7 +86,9 @@ typedef void (*lb_free_fn)(void *ptr, void *ctx);
  *   g            uniform body-force density, a test hook outside the paper's
  *                method (default 0; nonzero only for channel-flow checks);
  *   audit_every  fuse an FP64 mass/momentum audit and non-finite check into
- *                the collision every this many steps (0 = never);
+ *                the collision every this many steps (0 = never; every
+ *                100 steps costs 0.3% of the step time on MI355X, and is
+ *                the Python binding's default);
  *   stream       hipStream_t to run on (NULL = the null stream);
  *   alloc, free, alloc_ctx  optional device allocator pair;
  *   layout       LB_LAYOUT_AUTO (0, the default of a zeroed struct): the

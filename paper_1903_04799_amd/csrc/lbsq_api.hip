@@ -197,6 +197,13 @@ int rebuild_lists(lb_sim *s)
 }  // namespace
 
 // The step kernels' descriptor of a simulation, for time levels t = t0 + k.
+// Streaming blocks of the fluid launch: one per group of BLOCK cells, or
+// with static walls one per group that holds a cell other than a wall.
+static int stream_blocks(const lb_sim *s)
+{
+    return s->d_sgrp ? int(s->nsgrp) : int((uint64_t(s->args.box.n) + BLOCK - 1) / BLOCK);
+}
+
 void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
 {
     std::memset(&d, 0, sizeof(d));
@@ -218,6 +225,7 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
     d.all_base = s->d_lists + 2 * s->nmov + 2 + 2 * d.nbody;
     d.all_count = s->d_lists + 2 * s->nmov + 2 + 3 * d.nbody;
     d.shell = s->d_shell;
+    d.wmask = s->d_wmask;
     d.blkinfo = s->d_blkinfo;
     d.audit_part = s->d_audit_part;
     d.err = s->d_err;
@@ -228,14 +236,15 @@ void lbsq_fill_desc(const lb_sim *s, int64_t t0, int64_t t_end, SimDesc &d)
     d.t0 = t0;
     d.t_end = t_end;
     d.nblk_b = d.nbody > 0 ? s->nblk_all : 0;
-    d.nblk_s = int((s->args.box.n + BLOCK - 1) / BLOCK);
+    d.sgrp = s->d_sgrp;
+    d.nblk_s = stream_blocks(s);
 }
 
 // Blocks of the fluid and geometry launches of a simulation.
 void lbsq_sim_blocks(const lb_sim *s, uint32_t *fluid, uint32_t *geo)
 {
     const int nbody = int(s->bodies.size());
-    *fluid = uint32_t((s->args.box.n + BLOCK - 1) / BLOCK) + uint32_t(nbody > 0 ? s->nblk_all : 0);
+    *fluid = uint32_t(stream_blocks(s)) + uint32_t(nbody > 0 ? s->nblk_all : 0);
     *geo = uint32_t(geo_blocks(nbody, s->nblk_mov));
 }
 
@@ -288,10 +297,65 @@ int refresh_dens(lb_sim *s)
                : LB_EDEVICE;
 }
 
+// The groups of BLOCK cells the streaming blocks take: with static walls,
+// only those holding a cell other than a wall (walls never turn fluid), so
+// that all-wall regions cost the streaming launch no block.  own is the
+// host copy of the owners (walls OWN_WALL).
+int set_stream_groups(lb_sim *s, const uint8_t *own)
+{
+    const uint32_t n = s->args.box.n;
+    std::vector<uint32_t> g;
+    for (uint32_t b = 0; uint64_t(b) * BLOCK < n; ++b) {
+        const uint32_t e = uint32_t(std::min<uint64_t>(n, (uint64_t(b) + 1) * BLOCK));
+        for (uint32_t c = b * BLOCK; c < e; ++c)
+            if (own[c] != OWN_WALL) {
+                g.push_back(b);
+                break;
+            }
+    }
+    dev_free(s, s->d_sgrp);
+    s->d_sgrp = nullptr;
+    s->nsgrp = 0;
+    if (!g.empty()) {
+        s->d_sgrp = static_cast<uint32_t *>(dev_alloc(s, g.size() * sizeof(uint32_t)));
+        if (!s->d_sgrp) return LB_ENOMEM;
+        if (hipMemcpy(s->d_sgrp, g.data(), g.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+            return LB_EDEVICE;
+        s->nsgrp = uint32_t(g.size());
+    }
+    return upload_desc(s);
+}
+
+// Static walls of a simulation, from the host copy of its owners (walls
+// OWN_WALL).  With walls: room for every cell's wall mask (the device fills
+// it when it classifies the owners) and the list of streaming groups;
+// without: neither, and every group streams.  Either way the descriptor is
+// uploaded with the new pointers before anything is launched.
+int set_walls(lb_sim *s, const uint8_t *own, bool *walls_out)
+{
+    const uint32_t n = s->args.box.n;
+    bool walls = false;
+    for (uint32_t c = 0; c < n && !walls; ++c) walls = own[c] == OWN_WALL;
+    *walls_out = walls;
+    if (!walls) {
+        dev_free(s, s->d_sgrp);
+        dev_free(s, s->d_wmask);
+        s->d_sgrp = nullptr;
+        s->d_wmask = nullptr;
+        s->nsgrp = 0;
+        return upload_desc(s);
+    }
+    if (!s->d_wmask) {
+        s->d_wmask = static_cast<uint32_t *>(dev_alloc(s, size_t(n) * sizeof(uint32_t)));
+        if (!s->d_wmask) return LB_ENOMEM;
+    }
+    return set_stream_groups(s, own);
+}
+
 int classify_now(lb_sim *s)
 {
     if (!s->need_classify) return LB_OK;
-    if (launch_classify(s->args.box, s->own[s->cur], s->stream) != hipSuccess) return LB_EDEVICE;
+    if (launch_classify(s->args.box, s->own[s->cur], s->d_wmask, 1, s->stream) != hipSuccess) return LB_EDEVICE;
     s->need_classify = false;
     const int rc = mirror_owner(s);
     return rc == LB_OK ? refresh_dens(s) : rc;
@@ -351,6 +415,8 @@ int lb_destroy(lb_sim *s)
     }
     dev_free(s, s->d_lists);
     dev_free(s, s->d_shell);
+    dev_free(s, s->d_wmask);
+    dev_free(s, s->d_sgrp);
     dev_free(s, s->d_blkinfo);
     dev_free(s, s->d_desc);
     dev_free(s, s->d_batch_desc);
@@ -473,6 +539,9 @@ int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n)
     std::vector<uint8_t> h(n);
     for (size_t c = 0; c < n; ++c) h[c] = solid[c] ? OWN_WALL : OWN_FLUID;
     (void)hipSetDevice(s->device);
+    bool walls = false;
+    const int rc = set_walls(s, h.data(), &walls);
+    if (rc != LB_OK) return rc;
     for (int k = 0; k < 2; ++k)
         if (hipMemcpy(s->own[k], h.data(), n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
     s->need_classify = true;
@@ -856,6 +925,14 @@ int lb_load_state(lb_sim *s, const void *buf, size_t bytes)
     p += h.pop_bytes;
     for (int k = 0; k < 2; ++k)
         if (hipMemcpy(s->own[k], p, s->args.box.n, hipMemcpyHostToDevice) != hipSuccess) return LB_EDEVICE;
+    // static walls among the loaded owners (or none, replacing earlier
+    // ones): their wall masks, as the first step would have computed them;
+    // the loaded owner flags are kept
+    bool walls = false;
+    st = set_walls(s, reinterpret_cast<const uint8_t *>(p), &walls);
+    if (st != LB_OK) return st;
+    if (walls && launch_classify(s->args.box, s->own[s->cur], s->d_wmask, 0, s->stream) != hipSuccess)
+        return LB_EDEVICE;
     p += s->args.box.n;
     s->bodies.assign(h.nbody, DevBody{});
     if (h.nbody) {

@@ -383,21 +383,25 @@ __device__ __forceinline__ uint64_t post_slot(const Box &bx, int j, int x, int y
 
 template <class S, bool AUDIT, bool FORCE, int MODE>
 __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typename S::T> F, int64_t to_write,
-                                                     gptr<const uint8_t> own, double *__restrict__ audit_part,
-                                                     uint32_t blk)
+                                                     gptr<const uint8_t> own, gptr<const uint32_t> wmask,
+                                                     double *__restrict__ audit_part, uint32_t grp, uint32_t part)
 {
-    // F is the buffer read (and, in place, written); the pull layout writes
-    // the other buffer, to_write bytes away
+    // cells grp * BLOCK ... of the box; the audit partial goes to entry
+    // part.  F is the buffer read (and, in place, written); the pull layout
+    // writes the other buffer, to_write bytes away
     const Box &bx = a.box;
     const Planes<typename S::T> P(F, bx.dstride);
-    const uint32_t idx = blk * BLOCK + threadIdx.x;
+    const uint32_t idx = grp * BLOCK + threadIdx.x;
     const uint8_t o = idx < bx.n ? own[idx] : OWN_WALL;
     double am[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (o == OWN_FLUID || o == OWN_NB_WALL) {
         const Nbr nb(bx, idx);
         const uint32_t oi = pop_off(bx, idx);
         float f[Q];
-        if (o == OWN_FLUID) {
+        if (!__any(o == OWN_NB_WALL)) {
+            // no cell of the wave is next to a static wall: plain pulls (a
+            // wave-uniform branch, so that boxes without walls, and most
+            // waves of boxes with them, keep every load unconditional)
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 if (MODE == STEP_AA_ODD) f[i] = ld_plane<S>(P.p[opp(i)], pop_off(bx, nb.src(i)));
@@ -406,14 +410,21 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
             }
         } else {
             // no-slip walls: a population that would come from a wall is the
-            // cell's own opposite post-collision population
+            // cell's own opposite post-collision population.  Wall-adjacent
+            // cells take their sources' wall bits from the static mask, so
+            // they run the same loads as the other cells plus one load per
+            // wall link.
+            const uint32_t wm = o == OWN_NB_WALL ? wmask[idx] : 0u;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const uint32_t s = nb.src(i);
-                const bool fl = is_fluid(own[s]);
-                if (MODE == STEP_AB) f[i] = fl ? ld_plane_nt<S>(P.p[i], pop_off(bx, s)) : ld_plane_nt<S>(P.p[opp(i)], oi);
-                else if ((MODE == STEP_AA_ODD) == fl) f[i] = ld_plane<S>(P.p[opp(i)], pop_off(bx, s));
-                else f[i] = ld_plane<S>(P.p[i], oi);
+                // either load, never both: one destination per direction
+                const bool wall = (wm >> i) & 1u;
+                if (MODE == STEP_AA_ODD)
+                    f[i] = wall ? ld_plane<S>(P.p[i], oi) : ld_plane<S>(P.p[opp(i)], pop_off(bx, nb.src(i)));
+                else if (MODE == STEP_AB)
+                    f[i] = wall ? ld_plane_nt<S>(P.p[opp(i)], oi) : ld_plane_nt<S>(P.p[i], pop_off(bx, nb.src(i)));
+                else
+                    f[i] = wall ? ld_plane<S>(P.p[opp(i)], pop_off(bx, nb.src(i))) : ld_plane<S>(P.p[i], oi);
             }
         }
         float out[Q];
@@ -427,7 +438,7 @@ __device__ __forceinline__ void stream_collide_block(const StepArgs &a, gptr<typ
         }
         if (AUDIT) audit_add<S>(a, out, am);
     }
-    if (AUDIT) block_reduce<5>(am, audit_part + size_t(blk) * 5);
+    if (AUDIT) block_reduce<5>(am, audit_part + size_t(part) * 5);
 }
 
 // ---------------------------------------------------------------------------
@@ -887,8 +898,10 @@ __device__ __forceinline__ void arrive_and_update(const SimDesc &d, int c, int64
 // per step.  A simulation's blocks are contiguous; its first nblk_b blocks
 // take the cells next to a body (listed first so that their longer latency
 // overlaps the streaming blocks), the rest stream and collide the remaining
-// cells, BLOCK consecutive cells per block.  Audit partials: streaming block
-// j writes slot j, boundary block j writes slot nblk_s + j.
+// cells, BLOCK consecutive cells per block (with static walls, only the
+// groups of BLOCK cells that hold a cell other than a wall).  Audit
+// partials: streaming block j writes slot j, boundary block j writes slot
+// nblk_s + j.
 template <class S, bool AUDIT, bool FORCE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AUDIT ? 4 : S::waves))) void k_fluid(const SimDesc *__restrict__ D, BatchMap m, int64_t k)
 {
@@ -907,6 +920,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AUDIT ? 4
                                      : static_cast<const char *>(d.f2) - static_cast<const char *>(d.f))
                                 : 0;
     const gptr<const uint8_t> own = as_global(static_cast<const uint8_t *>(d.own[c]));
+    const gptr<const uint32_t> wmask = as_global(d.wmask);
     const int blk = int(blockIdx.x - m.fluid0[si]);
     if (blk < d.nblk_b) {
         const gptr<const float> dp = as_global(static_cast<const float *>(d.dens[c ^ 1]));
@@ -922,12 +936,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AUDIT ? 4
             boundary_block<S, AUDIT, FORCE, STEP_AA_EVEN>(d.a, F, 0, own, d.bodies[c], d.nbody, d.blkinfo, d.shell,
                                                           acc_set(d.acc, t), dp, dc, ap, blk);
         if (d.nbody <= FUSE_MAX) arrive_and_update(d, c, t);
-    } else if (ab) {
-        stream_collide_block<S, AUDIT, FORCE, STEP_AB>(d.a, F, to_write, own, d.audit_part, uint32_t(blk - d.nblk_b));
-    } else if (c) {
-        stream_collide_block<S, AUDIT, FORCE, STEP_AA_ODD>(d.a, F, 0, own, d.audit_part, uint32_t(blk - d.nblk_b));
     } else {
-        stream_collide_block<S, AUDIT, FORCE, STEP_AA_EVEN>(d.a, F, 0, own, d.audit_part, uint32_t(blk - d.nblk_b));
+        // streaming block j takes the j-th group of BLOCK cells, or with
+        // static walls the j-th group that holds a cell other than a wall
+        const uint32_t j = uint32_t(blk - d.nblk_b);
+        const uint32_t g = d.sgrp ? d.sgrp[j] : j;
+        if (ab)
+            stream_collide_block<S, AUDIT, FORCE, STEP_AB>(d.a, F, to_write, own, wmask, d.audit_part, g, j);
+        else if (c)
+            stream_collide_block<S, AUDIT, FORCE, STEP_AA_ODD>(d.a, F, 0, own, wmask, d.audit_part, g, j);
+        else
+            stream_collide_block<S, AUDIT, FORCE, STEP_AA_EVEN>(d.a, F, 0, own, wmask, d.audit_part, g, j);
     }
 }
 
@@ -1144,20 +1163,29 @@ __global__ __launch_bounds__(BLOCK) void k_geoconv(const SimDesc *__restrict__ D
 // ---------------------------------------------------------------------------
 // set-up, audit and readout kernels (outside the timed step)
 
-__global__ __launch_bounds__(BLOCK) void k_classify(Box bx, uint8_t *__restrict__ own)
+// Owner flags of the fluid cells (which of their neighbours are solid), and,
+// where static walls exist, every non-wall cell's wall mask: bit i set when
+// the source x - c_i of its direction i is a wall.  The mask depends on the
+// static walls only, so it is also right for body cells that later turn
+// fluid.
+__global__ __launch_bounds__(BLOCK) void k_classify(Box bx, uint8_t *__restrict__ own, uint32_t *__restrict__ wmask,
+                                                    int set_flags)
 {
     const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= bx.n) return;
     const uint8_t o = own[c];
-    if (!is_fluid(o)) return;
+    if (o == OWN_WALL) return;
     const int x = c % bx.nx, y = (c / bx.nx) % bx.ny, z = c / (uint32_t(bx.nx) * bx.ny);
-    bool nb_body = false, nb_wall = false;
+    bool nb_body = false;
+    uint32_t wm = 0;
     for (int i = 1; i < Q; ++i) {
         const uint8_t on = own[cell_of(bx, wrap(x + cx(i), bx.nx), wrap(y + cy(i), bx.ny), wrap(z + cz(i), bx.nz))];
         nb_body |= is_body(on);
-        nb_wall |= on == OWN_WALL;
+        // the neighbour x + c_i is the source of the opposite direction
+        if (on == OWN_WALL) wm |= 1u << opp(i);
     }
-    own[c] = nb_body ? OWN_NB_BODY : (nb_wall ? OWN_NB_WALL : OWN_FLUID);
+    if (wmask) wmask[c] = wm;
+    if (set_flags && is_fluid(o)) own[c] = nb_body ? OWN_NB_BODY : (wm ? OWN_NB_WALL : OWN_FLUID);
 }
 
 // mark (or, with check_only, test) the cells of body b
@@ -1384,9 +1412,9 @@ hipError_t launch_batch_step(int storage, const BatchLaunch &L)
     }
 }
 
-hipError_t launch_classify(const Box &bx, uint8_t *own, hipStream_t s)
+hipError_t launch_classify(const Box &bx, uint8_t *own, uint32_t *wmask, int set_flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_classify, dim3((bx.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, bx, own);
+    hipLaunchKernelGGL(k_classify, dim3((bx.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, bx, own, wmask, set_flags);
     return hipGetLastError();
 }
 

@@ -49,6 +49,8 @@ struct SimDesc {
     const int *all_ids, *all_start;  // every body and the block ranges of its shell cells
     const int *all_base, *all_count;  // where each body's shell cells sit in shell, and how many
     const uint32_t *shell;            // packed offsets relative to the floor of the body position
+    const uint32_t *wmask;            // per cell: bit i set when x - c_i is a static wall (null: no walls)
+    const uint32_t *sgrp;             // the groups of BLOCK cells holding a non-wall cell (null: every group)
     const int4 *blkinfo;              // per boundary block: body, first shell cell, cells, list position
     double *audit_part;
     int *err;
@@ -96,7 +98,9 @@ inline int geo_blocks(int nbody, int nblk_mov)
 }
 
 hipError_t launch_batch_step(int storage, const BatchLaunch &L);
-hipError_t launch_classify(const Box &bx, uint8_t *own, hipStream_t s);
+// Owner flags of the fluid cells (set_flags) and, if wmask is given, each
+// cell's static-wall mask.
+hipError_t launch_classify(const Box &bx, uint8_t *own, uint32_t *wmask, int set_flags, hipStream_t s);
 hipError_t launch_body_cells(const Box &bx, const DevBody *bodies, int b, int side, uint8_t *own, int check,
                              int *err, hipStream_t s);
 // Readouts of the state after a completed step: A is the buffer holding it

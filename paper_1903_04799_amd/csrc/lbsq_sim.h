@@ -40,6 +40,9 @@ struct lb_sim {
     std::vector<lbsq::DevBody> bodies;
     int *d_lists = nullptr;  // mov_ids | mov_start | all_ids | all_start | all_base | all_count
     uint32_t *d_shell = nullptr;  // packed shell-cell offsets of every body
+    uint32_t *d_wmask = nullptr;  // static-wall bits of each cell's sources (only with static walls)
+    uint32_t *d_sgrp = nullptr;   // groups of 256 cells holding a non-wall cell (only with static walls)
+    uint32_t nsgrp = 0;
     size_t shell_cap = 0;
     int4 *d_blkinfo = nullptr;  // per boundary block: body, first shell cell, cells, list position
     size_t blkinfo_cap = 0;

@@ -217,7 +217,7 @@ class Sim:
     """One periodic D3Q19 box with squirmers, resident on the GPU."""
 
     def __init__(self, shape, nu=1.0 / 6.0, magic=3.0 / 16.0, rho0=1.0, storage="f32",
-                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, g=(0.0, 0.0, 0.0), audit_every=0,
+                 scale_log2=None, wca_sigma=1.0, wca_eps=0.01, g=(0.0, 0.0, 0.0), audit_every=100,
                  stream=None, torch_memory=True, layout="auto"):
         L = load()
         nx, ny, nz = (int(v) for v in shape)

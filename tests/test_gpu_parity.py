@@ -382,7 +382,9 @@ def test_checkpoint_with_static_walls(saved_at, layout):
     """A state with static walls (a tube) saved after an even or odd step
     resumes bit for bit in a fresh handle that was never given the wall
     mask: the walls travel with the saved owners, and the streaming path's
-    per-cell wall masks are rebuilt from them."""
+    per-cell wall masks and its list of non-wall cell groups are rebuilt
+    from them.  A state without walls loaded into a handle with walls
+    resumes as its original did."""
     note("checkpoint with static walls (saved after %d steps, %s)" % (saved_at, layout))
     lbsq = gpu()
     shape = (30, 26, 28)
@@ -410,6 +412,23 @@ def test_checkpoint_with_static_walls(saved_at, layout):
     assert np.array_equal(own_a, own_c) and (own_a == 255).sum() == mask.sum()
     a.close()
     c.close()
+    # and the other way: a state without walls loaded into a handle that was
+    # given walls drops them (every group of cells streams again)
+    b = fresh(walls=False)
+    b.step(saved_at)
+    blob = b.save_state()
+    b.step(50)
+    d = fresh(walls=True)
+    d.load_state(blob)
+    d.step(50)
+    assert np.array_equal(b.populations(), d.populations())
+    for k in ("pos", "e", "v", "w"):
+        assert np.array_equal(b.body(0)[k], d.body(0)[k])
+    _, _, own_b = b.fields()
+    _, _, own_d = d.fields()
+    assert np.array_equal(own_b, own_d) and not (own_d == 255).any()
+    b.close()
+    d.close()
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
