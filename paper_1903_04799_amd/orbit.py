@@ -47,17 +47,27 @@ def classify(gaps, angles, contact_gap=1.5, release_gap=16.0):
     return "undecided", len(gaps) - 1
 
 
-def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, max_steps=600000,
+def start_geometry(A, R, n, gap0, angle_deg=0.0, y0=0.0):
+    """Obstacle centre, swimmer start and heading.  The obstacle sits at the
+    box centre; the swimmer starts on the -x side with its surface gap0 from
+    the obstacle's (measured along x), displaced by y0 along +y, heading
+    along +x turned by angle_deg towards +y.  The paper breaks the symmetry
+    of the radial approach either way: by a small angle (its text) or by a
+    small offset y0 (its figure's inset)."""
+    c = np.array([n / 2.0, n / 2.0, n / 2.0])
+    d0 = A + R + gap0
+    start = c + np.array([-d0, float(y0), 0.0])
+    th = math.radians(angle_deg)
+    return c, start, (math.cos(th), math.sin(th), 0.0)
+
+
+def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, y0=0.0, max_steps=600000,
               every=2000, storage="f16", layout="auto", contact_gap=1.5, release_gap=16.0, log=None):
     """One run; stops as soon as the outcome is decided.  Returns a dict with
     the outcome, the step it was decided at, and the sampled trajectory
     (step, surface gap, swept angle in degrees, heading angle to the
     obstacle centre in degrees)."""
-    c = np.array([n / 2.0, n / 2.0, n / 2.0])
-    d0 = A + R + gap0
-    start = c - np.array([d0, 0.0, 0.0])
-    th = math.radians(angle_deg)
-    e = (math.cos(th), math.sin(th), 0.0)
+    c, start, e = start_geometry(A, R, n, gap0, angle_deg, y0)
     s = lbsq.Sim((n, n, n), storage=storage, layout=layout)
     s.add_squirmer(tuple(c), (1.0, 0.0, 0.0), A, B1=0.0, mode="fixed")
     s.add_squirmer(tuple(start), e, R, B1=B1, beta=beta)
@@ -96,7 +106,7 @@ def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, max
     return {"beta": beta, "outcome": outcome, "decided_at": rows[k][0] if rows else 0, "steps": steps,
             "min_gap": float(min(gaps)) if gaps else None,
             "max_swept_deg": float(max(abs(a) for a in angles) * 180.0 / math.pi) if angles else 0.0,
-            "trajectory": rows, "A": A, "R": R, "n": n, "B1": B1, "gap0": gap0, "angle_deg": angle_deg,
+            "trajectory": rows, "A": A, "R": R, "n": n, "B1": B1, "gap0": gap0, "angle_deg": angle_deg, "y0": y0,
             "storage": storage, "seconds": time.time() - t0}
 
 

@@ -6,6 +6,8 @@ synthetic trajectories and a fake run.  The GPU runs themselves are
 recorded in the design notes."""
 import math
 
+import numpy as np
+
 from paper_1903_04799_amd import orbit
 
 
@@ -37,3 +39,19 @@ def test_bisection_brackets_the_critical_beta():
     (lo, hi), runs = orbit.bisect(-50.0, -20.0, tol=1.0, run=fake)
     assert lo <= critical <= hi and hi - lo <= 1.0
     assert all(r["outcome"] == ("orbit" if r["beta"] < critical else "scatter") for r in runs)
+
+
+def test_start_geometry_angle_or_offset():
+    A, R, n, gap0 = 96.0, 8.0, 320, 4.0
+    # an angled start: the surface gap is gap0, the heading turned by the angle
+    c, start, e = orbit.start_geometry(A, R, n, gap0, angle_deg=30.0)
+    assert abs(np.linalg.norm(start - c) - A - R - gap0) < 1e-12
+    assert abs(math.degrees(math.atan2(e[1], e[0])) - 30.0) < 1e-12
+    # an offset start along +x: the heading line passes the obstacle centre
+    # at distance y0 (the impact parameter of the paper's inset)
+    c, start, e = orbit.start_geometry(A, R, n, gap0, y0=2.5)
+    rel = c - start
+    miss = abs(rel[0] * e[1] - rel[1] * e[0])
+    assert e == (1.0, 0.0, 0.0) and abs(miss - 2.5) < 1e-12
+    # both stay in the z = n/2 plane, where the swept angle is measured
+    assert start[2] == c[2] == n / 2.0
