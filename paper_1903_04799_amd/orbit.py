@@ -62,13 +62,18 @@ def start_geometry(A, R, n, gap0, angle_deg=0.0, y0=0.0):
 
 
 def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, y0=0.0, max_steps=600000,
-              every=2000, storage="f16", layout="auto", contact_gap=1.5, release_gap=16.0, log=None):
+              every=2000, storage="f16", layout="auto", wca_sigma=1.0, wca_eps=0.01, contact_gap=None,
+              release_gap=16.0, log=None):
     """One run; stops as soon as the outcome is decided.  Returns a dict with
     the outcome, the step it was decided at, and the sampled trajectory
     (step, surface gap, swept angle in degrees, heading angle to the
-    obstacle centre in degrees)."""
+    obstacle centre in degrees).  The contact repulsion (WCA, surface to
+    surface) has range 2^(1/6) wca_sigma; contact is a gap below that range
+    plus 0.4 cells unless contact_gap is given."""
+    if contact_gap is None:
+        contact_gap = 2.0 ** (1.0 / 6.0) * wca_sigma + 0.4
     c, start, e = start_geometry(A, R, n, gap0, angle_deg, y0)
-    s = lbsq.Sim((n, n, n), storage=storage, layout=layout)
+    s = lbsq.Sim((n, n, n), storage=storage, layout=layout, wca_sigma=wca_sigma, wca_eps=wca_eps)
     s.add_squirmer(tuple(c), (1.0, 0.0, 0.0), A, B1=0.0, mode="fixed")
     s.add_squirmer(tuple(start), e, R, B1=B1, beta=beta)
     phi0 = math.atan2(start[1] - c[1], start[0] - c[0])
@@ -107,6 +112,7 @@ def orbit_run(beta, A=50.0, R=8.0, n=384, B1=1e-3, gap0=16.0, angle_deg=5.0, y0=
             "min_gap": float(min(gaps)) if gaps else None,
             "max_swept_deg": float(max(abs(a) for a in angles) * 180.0 / math.pi) if angles else 0.0,
             "trajectory": rows, "A": A, "R": R, "n": n, "B1": B1, "gap0": gap0, "angle_deg": angle_deg, "y0": y0,
+            "wca_sigma": wca_sigma, "wca_eps": wca_eps,
             "storage": storage, "seconds": time.time() - t0}
 
 
