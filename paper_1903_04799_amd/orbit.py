@@ -22,6 +22,8 @@ value, as the paper does once one of each is known.
 """
 from __future__ import annotations
 
+import argparse
+import json
 import math
 import time
 
@@ -131,3 +133,65 @@ def bisect(beta_orbit, beta_scatter, tol=1.0, run=orbit_run, **kw):
         else:
             hi = mid
     return (lo, hi), runs
+
+
+def main(argv=None):
+    """Bracket the critical beta at one obstacle size: check that the first
+    beta orbits and the second does not (unless --known), then bisect until
+    the bracket is narrower than --tol or --budget seconds have passed.
+    Prints one line per run and the bracket; --out writes every run."""
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--A", type=float, default=50.0, help="obstacle radius")
+    ap.add_argument("--R", type=float, default=8.0, help="squirmer radius")
+    ap.add_argument("--n", type=int, default=320, help="cubic box edge")
+    ap.add_argument("--B1", type=float, default=2e-3)
+    ap.add_argument("--sigma", type=float, default=3.0, help="WCA range parameter")
+    ap.add_argument("--eps", type=float, default=0.01, help="WCA strength")
+    ap.add_argument("--angle", type=float, default=30.0, help="heading off radial, degrees")
+    ap.add_argument("--gap0", type=float, default=5.0, help="start surface gap")
+    ap.add_argument("--max-steps", type=int, default=450000)
+    ap.add_argument("--storage", default="f16")
+    ap.add_argument("--orbit", type=float, default=-45.0, help="a beta expected to orbit")
+    ap.add_argument("--scatter", type=float, default=-20.0, help="a beta expected not to")
+    ap.add_argument("--known", action="store_true", help="the two ends are known; do not rerun them")
+    ap.add_argument("--tol", type=float, default=1.5)
+    ap.add_argument("--budget", type=float, default=1e9, help="start no run after this many seconds")
+    ap.add_argument("--out", default=None, help="JSON file for every run")
+    a = ap.parse_args(argv)
+    t0 = time.time()
+    runs = []
+
+    def one(beta):
+        r = orbit_run(beta, A=a.A, R=a.R, n=a.n, B1=a.B1, gap0=a.gap0, angle_deg=a.angle, max_steps=a.max_steps,
+                      storage=a.storage, wca_sigma=a.sigma, wca_eps=a.eps)
+        runs.append(r)
+        print("beta %g: %s at step %d (min gap %.2f, swept %.1f deg, %.0f s)"
+              % (beta, r["outcome"], r["decided_at"], r["min_gap"], r["max_swept_deg"], r["seconds"]), flush=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(runs, f)
+        return r
+
+    lo, hi = a.orbit, a.scatter
+    if not a.known:
+        if one(lo)["outcome"] != "orbit":
+            print("no bracket: beta %g does not orbit" % lo)
+            return 1
+        if one(hi)["outcome"] == "orbit":
+            print("no bracket: beta %g orbits too" % hi)
+            return 1
+
+    while abs(hi - lo) > a.tol and time.time() - t0 < a.budget:
+        mid = round(0.5 * (lo + hi))
+        if mid in (lo, hi):
+            break
+        if one(mid)["outcome"] == "orbit":
+            lo = mid
+        else:
+            hi = mid
+    print("bracket: beta %g orbits, beta %g does not (A/R = %g)" % (lo, hi, a.A / a.R))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -55,3 +55,29 @@ def test_start_geometry_angle_or_offset():
     assert e == (1.0, 0.0, 0.0) and abs(miss - 2.5) < 1e-12
     # both stay in the z = n/2 plane, where the swept angle is measured
     assert start[2] == c[2] == n / 2.0
+
+
+def test_command_line_brackets_and_checks_its_ends(monkeypatch, capsys, tmp_path):
+    critical = -29.5
+    calls = []
+
+    def fake(beta, **kw):
+        calls.append(beta)
+        return {"beta": beta, "outcome": "orbit" if beta <= critical else "scatter", "decided_at": 1000,
+                "min_gap": 2.7, "max_swept_deg": 100.0, "seconds": 0.0}
+
+    monkeypatch.setattr(orbit, "orbit_run", fake)
+    out = tmp_path / "runs.json"
+    assert orbit.main(["--orbit", "-45", "--scatter", "-20", "--tol", "1.5", "--out", str(out)]) == 0
+    assert calls[:2] == [-45.0, -20.0]
+    line = capsys.readouterr().out.strip().splitlines()[-1]
+    assert line == "bracket: beta -30 orbits, beta -29 does not (A/R = 6.25)"
+    import json
+    assert [r["beta"] for r in json.loads(out.read_text())] == calls
+    # with known ends only the midpoints run
+    calls.clear()
+    assert orbit.main(["--orbit", "-30", "--scatter", "-6", "--known", "--A", "96"]) == 0
+    assert -30.0 not in calls and -6.0 not in calls and calls[0] == -18.0
+    # ends on the wrong side: no bracket
+    assert orbit.main(["--orbit", "-20", "--scatter", "-10"]) == 1
+    assert orbit.main(["--orbit", "-45", "--scatter", "-40"]) == 1
