@@ -163,7 +163,7 @@ def main(argv=None):
 
     def one(beta):
         r = orbit_run(beta, A=a.A, R=a.R, n=a.n, B1=a.B1, gap0=a.gap0, angle_deg=a.angle, max_steps=a.max_steps,
-                      storage=a.storage, wca_sigma=a.sigma, wca_eps=a.eps)
+                      storage=a.storage, wca_sigma=a.sigma, wca_eps=a.eps, log=lambda m: print(m, flush=True))
         runs.append(r)
         print("beta %g: %s at step %d (min gap %.2f, swept %.1f deg, %.0f s)"
               % (beta, r["outcome"], r["decided_at"], r["min_gap"], r["max_swept_deg"], r["seconds"]), flush=True)
