@@ -421,3 +421,28 @@ def test_tube_scene_on_axis(beta):
     # FP32 round-off breaks the mirror symmetry only at the 1e-7 level
     assert off_axis < 1e-3 and b["e"][2] > 1.0 - 1e-6
     assert abs(drho) < 5e-5
+
+
+def test_E6_orbit_and_scatter_either_side_of_the_boundary():
+    """The orbit/scatter study at the paper's smallest obstacle, A/R = 6.25
+    (A = 50, R = 8): the paper places the critical -beta between 32 and 34,
+    and the bisection here between 29 and 30 (320^3, B1 = 2e-3, start 5
+    cells off at 30 degrees, contact range sigma = 3).  Well on either side:
+    beta = -45 orbits, sweeping past half a revolution at a steady gap
+    within the contact range; beta = -20 touches and leaves.  Each run stops
+    as soon as it is decided (about 70,000-80,000 steps)."""
+    gpu()
+    from paper_1903_04799_amd import orbit
+    out = {}
+    for beta in (-45.0, -20.0):
+        note("E6: A = 50, R = 8, 320^3, sigma = 3, beta = %g" % beta)
+        r = orbit.orbit_run(beta, A=50.0, R=8.0, n=320, B1=2e-3, gap0=5.0, angle_deg=30.0, max_steps=200000,
+                            wca_sigma=3.0)
+        note("  %s at step %d, min gap %.2f, swept %.1f deg" % (r["outcome"], r["decided_at"], r["min_gap"],
+                                                                r["max_swept_deg"]))
+        out[beta] = r
+    orb, sca = out[-45.0], out[-20.0]
+    assert orb["outcome"] == "orbit" and orb["max_swept_deg"] > 180.0
+    # it circles at the contact distance, never overlapping
+    assert 2.0 < orb["min_gap"] < 2.0 ** (1.0 / 6.0) * 3.0 + 0.4
+    assert sca["outcome"] == "scatter" and sca["max_swept_deg"] < 180.0 and sca["min_gap"] > 2.0
