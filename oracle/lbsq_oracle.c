@@ -22,8 +22,8 @@
  *   - WCA contact repulsion, eq. (wca);
  *   - symplectic Euler rigid-body integration (text after eq. (wca)).
  *
- * Readings taken where the printed text is garbled or silent (each one is
- * listed with its justification in the design notes of the repository):
+ * Readings taken where the printed text is garbled or silent (each with its
+ * reason after it):
  *   - equilibrium coefficients 9/2 and 3/2 (the printed 1/6 cannot give the
  *     Navier-Stokes momentum flux);  u carries the 1/rho;
  *   - lambda_e, lambda_o are relaxation *rates*; nu = (1/lambda_e - 1/2)/3;

@@ -6,7 +6,8 @@ computed independently in exact integer arithmetic, or a symmetry.  A plausible
 slip anywhere in the oracle (a dropped term, a wrong sign or index, a
 transposed operand) breaks at least one of them.
 
-Labels P1..P14 follow the pin list of the design notes.
+Labels P1..P15 name the pins; each test states what it fixes and where the
+paper (or the mathematics) fixes it.
 """
 import itertools
 import math

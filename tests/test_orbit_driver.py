@@ -2,8 +2,8 @@
 sampled trajectory by the paper's criterion (Sec. "Scattering off and
 Orbiting around a Stationary Spherical Obstacle": an orbit revolves more
 than halfway around the obstacle) and the bisection over beta, on
-synthetic trajectories and a fake run.  The GPU runs themselves are
-recorded in the design notes."""
+synthetic trajectories and a fake run.  A GPU run of the driver on each
+side of the boundary is in test_gpu_physics.py (E6)."""
 import math
 
 import numpy as np
