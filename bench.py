@@ -43,6 +43,7 @@ BYTES_PER_UPDATE = {"f32": 152, "f16": 76, "bf16": 76}
 PROFILES = Path(ROOT) / "profiles"
 TRACE_256 = PROFILES / "k_fluid_256cube_kernel_trace.md"
 TRAFFIC_256 = PROFILES / "k_fluid_256cube_traffic.md"
+TRACE_TUBE = PROFILES / "k_fluid_tube_kernel_trace.md"
 LEGS = ("value", "roofline", "fp16", "tube", "audit", "serve", "cpu")
 
 
@@ -427,17 +428,30 @@ def main():
             t[st] = r
         n = ts[0] * ts[1] * ts[2]
         # what the wall costs: groups of 256 consecutive cells (x fastest)
-        # that hold only walls get no streaming block; a wall cell in another
-        # group costs its owner byte, a wall-adjacent fluid cell 4 bytes of
-        # wall mask on top of its populations
+        # that hold only walls get no streaming block; in the other groups
+        # a wall cell's lane loads only its owner byte, but the fluid lanes'
+        # loads bring in whole 128-byte lines, wall slots included (the
+        # committed counter traffic below)
         wall = mask.reshape(-1).astype(bool)
         ng = (n + 255) // 256
-        grp_wall = np.ones(ng, dtype=bool)
-        np.logical_and.reduceat(wall, np.arange(0, n, 256), out=grp_wall)
+        grp_wall = np.logical_and.reduceat(wall, np.arange(0, n, 256))
         walls_streamed = int(wall.reshape(ng, 256)[~grp_wall].sum()) if n % 256 == 0 else None
+        fl = t["f32"]["n_fluid"]
+        traffic = profiled(TRACE_TUBE, "traffic_bytes_per_launch_f32_tube")
+        prof_us = profiled(TRACE_TUBE, "k_fluid_us_f32_tube")
+        # the same scene rotated so that the tube runs along x, the fastest
+        # axis of the cell numbering: every x-row is then all wall or all fluid
+        tx = (ts[2], ts[1], ts[0])
+        mask_x = tube_mask(*tx, 24.0, axis="x")
+        ax = {}
+        for st in ("f32", "f16"):
+            ax[st] = run_gpu(st, tx, 12.0, args.beta, args.steps, args.warmup, "auto", mask=mask_x,
+                             pos=(256.0, 48.0, 48.0), e=(1.0, 0.0, 0.0))
+        wall_x = mask_x.reshape(-1).astype(bool)
+        grp_x = np.logical_and.reduceat(wall_x, np.arange(0, n, 256))
         out["tube"] = {"workload": "squirmer R = 12 on the axis of a tube of radius 24 in 96x96x512 "
                                    "(static no-slip wall, 80% of the cells)",
-                       "cells": n, "fluid_cells": t["f32"]["n_fluid"],
+                       "cells": n, "fluid_cells": fl,
                        "mflups_f32": round(t["f32"]["mlups"], 1), "mflups_f16": round(t["f16"]["mlups"], 1),
                        "kernel_us_f32": round(t["f32"]["kernel_us"], 2),
                        "kernel_us_f16": round(t["f16"]["kernel_us"], 2),
@@ -445,12 +459,24 @@ def main():
                        "fluid_gbs_f16": round(t["f16"]["kernel_gbs"], 1),
                        "frac_f32": round(t["f32"]["kernel_gbs"] / HBM_PEAK_GBS, 4),
                        "streamed_groups": int((~grp_wall).sum()), "groups": int(ng),
-                       "bytes_per_wall_cell": (round(walls_streamed / int(wall.sum()), 4)
-                                               if walls_streamed is not None else None),
-                       "note": "wall populations are never read or written; groups of 256 cells that hold "
-                               "only walls get no block, and a wall cell in another group costs its owner "
-                               "byte (bytes_per_wall_cell is the average over all wall cells); the GB/s "
-                               "count 152 / 76 B per fluid-cell update only"}
+                       "requested_bytes_per_wall_cell": (round(walls_streamed / int(wall.sum()), 4)
+                                                         if walls_streamed is not None else None),
+                       "traffic": traffic, "traffic_unit": "bytes/launch (FP32, committed rocprofv3 counters)",
+                       "traffic_over_fluid_algorithmic": (round(traffic / (152.0 * fl), 3) if traffic else None),
+                       "profile_kernel_us_f32": prof_us,
+                       "note": "GB/s count 152 / 76 B per fluid-cell update only. Groups of 256 cells that hold "
+                               "only walls get no block; a wall cell elsewhere requests its owner byte "
+                               "(requested_bytes_per_wall_cell averages that over all wall cells), but shares "
+                               "128-byte lines with fluid cells, whose loads bring its slots in: the counter "
+                               "traffic is the measured cost",
+                       "along_x": {"workload": "the same scene rotated: 512x96x96, tube along x",
+                                   "mflups_f32": round(ax["f32"]["mlups"], 1),
+                                   "mflups_f16": round(ax["f16"]["mlups"], 1),
+                                   "kernel_us_f32": round(ax["f32"]["kernel_us"], 2),
+                                   "kernel_us_f16": round(ax["f16"]["kernel_us"], 2),
+                                   "fluid_gbs_f32": round(ax["f32"]["kernel_gbs"], 1),
+                                   "frac_f32": round(ax["f32"]["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                                   "streamed_groups": int((~grp_x).sum())}}
     if "audit" in legs:
         # the fused FP64 audit: a step with it against one without
         plain = run_gpu("f32", shape, args.R, args.beta, args.steps, args.warmup, args.layout)

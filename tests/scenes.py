@@ -16,9 +16,16 @@ def noise(seed, shape, amplitude):
     return amplitude * np.random.default_rng(seed).standard_normal(shape)
 
 
-def tube_mask(nx, ny, nz, radius, centre=None):
+def tube_mask(nx, ny, nz, radius, centre=None, axis="z"):
     """Static wall mask [z, y, x]: cells whose centre lies at or beyond
-    `radius` from the tube axis (parallel to z)."""
+    `radius` from the tube axis (parallel to z, or to x with axis="x";
+    centre gives the axis' position in the other two coordinates)."""
+    if axis == "x":
+        cy, cz = centre if centre is not None else (ny / 2.0, nz / 2.0)
+        y = np.arange(ny) + 0.5
+        z = np.arange(nz) + 0.5
+        r2 = (y[None, :] - cy) ** 2 + (z[:, None] - cz) ** 2
+        return np.broadcast_to((r2 >= radius ** 2)[:, :, None], (nz, ny, nx)).astype(np.uint8)
     cx, cy = centre if centre is not None else (nx / 2.0, ny / 2.0)
     x = np.arange(nx) + 0.5
     y = np.arange(ny) + 0.5

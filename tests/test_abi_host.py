@@ -168,6 +168,25 @@ def test_profile_summaries_match_the_kernel_sources():
             assert 0.6 * bench.HBM_PEAK_GBS <= gbs <= bench.HBM_PEAK_GBS, (storage, lay, gbs)
 
 
+def test_tube_profile_matches_the_kernel_sources():
+    """The committed tube summary (96 x 96 x 512, tube of radius 24, 916,396
+    fluid cells) was taken on the kernel sources as they stand, and its
+    counter traffic is at least the fluid cells' algorithmic bytes and at
+    most the cost of reading and writing every cell of the groups of 256
+    cells that hold a fluid cell (2,359,296 cells: no group of walls alone
+    is streamed)."""
+    bench = _bench()
+    fluid, streamed = 916396, 2359296
+    for storage in ("f32", "f16"):
+        t = bench.profiled(bench.TRACE_TUBE, "traffic_bytes_per_launch_%s_tube" % storage)
+        us = bench.profiled(bench.TRACE_TUBE, "k_fluid_us_%s_tube" % storage)
+        assert t is not None and us is not None, "profiles/k_fluid_tube_kernel_trace.md predates the kernel sources"
+        b = bench.BYTES_PER_UPDATE[storage]
+        assert b * fluid <= t <= b * streamed, (storage, t)
+        # what the memory system moved stays within the HBM peak
+        assert t / (us * 1e-6) / 1e9 <= bench.HBM_PEAK_GBS, (storage, t, us)
+
+
 def test_profile_figures_are_ignored_once_the_kernels_change(tmp_path):
     """A summary whose hash does not match the kernel sources gives no
     figures (bench.py then reports null rather than a stale number)."""
