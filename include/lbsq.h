@@ -145,7 +145,13 @@ int lb_create(const lb_params *p, lb_sim **out);
 
 /* Static no-slip walls (bounce-back with zero wall velocity, the no-slip
  * rule of Sec. "Numerical Method"): solid[c] != 0 marks cell c as wall.  n
- * must equal nx*ny*nz.  Only before the first step and before any body.  */
+ * must equal nx*ny*nz.  Only before the first step and before any body.
+ * A mask with walls takes 4 more bytes of device memory per cell (each
+ * cell's wall links) and a list of the groups of 256 cells that hold a
+ * non-wall cell (groups of walls alone are never streamed); a mask without
+ * walls releases both.  Cells are numbered x fastest, so a channel along x
+ * keeps wall and fluid cells in separate cache lines and moves least
+ * memory.  LB_ENOMEM if the masks cannot be allocated.                    */
 int lb_set_static_mask(lb_sim *s, const uint8_t *solid, size_t n);
 
 /* Add a body (see lb_squirmer); *id receives its index (0, 1, ...).  The
