@@ -189,7 +189,9 @@ def main(argv=None):
             lo = mid
         else:
             hi = mid
-    print("bracket: beta %g orbits, beta %g does not (A/R = %g)" % (lo, hi, a.A / a.R))
+    ran = {r["beta"] for r in runs}
+    note = "" if lo in ran and hi in ran else " (an end taken as known, not run)"
+    print("bracket: beta %g orbits, beta %g does not (A/R = %g)%s" % (lo, hi, a.A / a.R, note))
     return 0
 
 

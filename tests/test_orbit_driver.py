@@ -74,10 +74,18 @@ def test_command_line_brackets_and_checks_its_ends(monkeypatch, capsys, tmp_path
     assert line == "bracket: beta -30 orbits, beta -29 does not (A/R = 6.25)"
     import json
     assert [r["beta"] for r in json.loads(out.read_text())] == calls
-    # with known ends only the midpoints run
+    # with known ends only the midpoints run, and the bracket says when an
+    # end of it was not run
     calls.clear()
     assert orbit.main(["--orbit", "-30", "--scatter", "-6", "--known", "--A", "96"]) == 0
     assert -30.0 not in calls and -6.0 not in calls and calls[0] == -18.0
+    # every midpoint scattered, so the orbiting end is the unrun -30
+    line = capsys.readouterr().out.strip().splitlines()[-1]
+    assert line == "bracket: beta -30 orbits, beta -29 does not (A/R = 12) (an end taken as known, not run)"
+    calls.clear()
+    assert orbit.main(["--orbit", "-40", "--scatter", "-20", "--known"]) == 0
+    line = capsys.readouterr().out.strip().splitlines()[-1]
+    assert line == "bracket: beta -30 orbits, beta -29 does not (A/R = 6.25)" and -40.0 not in calls
     # ends on the wrong side: no bracket
     assert orbit.main(["--orbit", "-20", "--scatter", "-10"]) == 1
     assert orbit.main(["--orbit", "-45", "--scatter", "-40"]) == 1
